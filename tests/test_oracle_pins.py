@@ -1,0 +1,236 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle step against something other than its own formula:
+a different equation of the paper (pressure tensor, chemical potential),
+exactness properties of the stencils, orthogonality of the MRT basis, brute-force
+streaming, exact conservation, and a special case in which MRT must reduce to BGK.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0812_1282_amd import workloads as wl
+from tests.helpers import make_oracle, orc_params
+
+# Lattice vectors typed from the definition in Sec. III.A:
+# e0 = (0,0), e1,2 = (+-1,0), e3,4 = (0,+-1), e5,6 = (+-1,+-1), e7,8 = (-+1,+-1).
+E = np.array([(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (-1, 1), (1, -1)])
+A_LANDAU = 0.04  # the paper's a
+
+
+def test_lattice_vectors_match_definition():
+    ex, ey, *_ = oracle.lattice()
+    assert np.array_equal(np.stack([ex, ey], 1), E)
+
+
+def _pressure_tensor(rho, phi, gx, gy, lap, kappa, a):
+    """Eq. (pressten) with p0 of Eq. (p0), c = 1."""
+    p0 = rho / 3.0 + a * (-0.5 * phi ** 2 + 0.75 * phi ** 4)
+    iso = p0 - kappa * phi * lap - 0.5 * kappa * (gx * gx + gy * gy)
+    g = np.array([gx, gy])
+    return iso * np.eye(2) + kappa * np.outer(g, g)
+
+
+@pytest.mark.parametrize("step2", [False, True])
+def test_equilibrium_moments_give_pressure_tensor_and_mu(step2):
+    """Sum f^eq = rho, sum f^eq e = rho u, sum f^eq e e = P + rho u u (Eq. (pressten));
+    sum g^eq = phi, sum g^eq e = phi u, sum g^eq e e = Gamma mu I + phi u u with mu of
+    Eq. (chempot). Under Step 2 the f^eq velocity is zero."""
+    rng = np.random.default_rng(11)
+    kappa, Gamma = 0.04, 0.37
+    P = oracle.make_params(8, 8, A=-A_LANDAU, B=A_LANDAU, kappa=kappa, Gamma=Gamma)
+    for _ in range(40):
+        rho = rng.uniform(0.7, 1.3)
+        phi = rng.uniform(-1.2, 1.2)
+        ux, uy = rng.uniform(-0.1, 0.1, 2)
+        gx, gy, lap = rng.uniform(-0.3, 0.3, 3)
+        uf = (0.0, 0.0) if step2 else (ux, uy)
+        feq, geq = oracle.equilibria_node(P, rho, phi, ux, uy, gx, gy, lap, uf[0], uf[1])
+        uvf = np.array(uf)
+        uv = np.array([ux, uy])
+        assert feq.sum() == pytest.approx(rho, abs=1e-15)
+        np.testing.assert_allclose(E.T @ feq, rho * uvf, atol=2e-16)
+        second = np.einsum("i,ia,ib->ab", feq, E, E)
+        expect = _pressure_tensor(rho, phi, gx, gy, lap, kappa, A_LANDAU) + rho * np.outer(uvf, uvf)
+        np.testing.assert_allclose(second, expect, atol=5e-16)
+        mu = A_LANDAU * (-phi + phi ** 3) - kappa * lap
+        assert geq.sum() == pytest.approx(phi, abs=1e-15)
+        np.testing.assert_allclose(E.T @ geq, phi * uv, atol=2e-16)
+        np.testing.assert_allclose(np.einsum("i,ia,ib->ab", geq, E, E),
+                                   Gamma * mu * np.eye(2) + phi * np.outer(uv, uv), atol=5e-16)
+
+
+def test_mrt_basis():
+    """Rows of M are orthogonal with norms (9,36,36,6,12,6,12,4,4); M^-1 M = I;
+    rows 0, 3, 5 give rho, j_x, j_y (Sec. III.B); rows 7 and 8 are the traceless
+    stress moments e_x^2 - e_y^2 and e_x e_y, the modes that carry the viscosity."""
+    M, Minv = oracle.mrt_matrices()
+    G = M @ M.T
+    np.testing.assert_array_equal(G, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]))
+    np.testing.assert_allclose(Minv @ M, np.eye(9), atol=1e-15)
+    np.testing.assert_allclose(M @ Minv, np.eye(9), atol=1e-15)
+    ex, ey = E[:, 0], E[:, 1]
+    np.testing.assert_array_equal(M[0], np.ones(9))
+    np.testing.assert_array_equal(M[3], ex)
+    np.testing.assert_array_equal(M[5], ey)
+    np.testing.assert_array_equal(M[7], ex * ex - ey * ey)
+    np.testing.assert_array_equal(M[8], ex * ey)
+
+
+def test_stencils_exact_on_quadratics():
+    """The stencils of Eq. (best) differentiate polynomials of degree <= 2 exactly
+    (read at nodes away from the periodic seam)."""
+    n = 16
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    cases = {
+        "x": (x, 1.0, 0.0, 0.0),
+        "y": (y, 0.0, 1.0, 0.0),
+        "x2": (x * x, 2 * x, 0.0, 2.0),
+        "y2": (y * y, 0.0, 2 * y, 2.0),
+        "xy": (x * y, y, x, 0.0),
+        "c": (np.full_like(x, 3.0), 0.0, 0.0, 0.0),
+    }
+    inner = (slice(2, n - 2), slice(2, n - 2))
+    for name, (field, ddx, ddy, lap) in cases.items():
+        gx, gy, gl = oracle.gradients(field)
+        np.testing.assert_allclose(gx[inner], np.broadcast_to(ddx, field.shape)[inner], atol=1e-12,
+                                   err_msg=name)
+        np.testing.assert_allclose(gy[inner], np.broadcast_to(ddy, field.shape)[inner], atol=1e-12,
+                                   err_msg=name)
+        np.testing.assert_allclose(gl[inner], np.broadcast_to(lap, field.shape)[inner], atol=1e-12,
+                                   err_msg=name)
+
+
+def test_stencils_isotropic_and_rotation_consistent():
+    """d/dy is d/dx on the field rotated by 90 degrees, and the Laplacian is
+    invariant under that rotation (Eq. (best) is isotropic)."""
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((12, 12))
+    gx, gy, gl = oracle.gradients(f)
+    # rot90: fr(x', y') = f(x = n-1-y', y = x'), so d/dx' of fr is d/dy of f
+    fr = np.rot90(f, k=1)
+    rx, ry, rl = oracle.gradients(np.ascontiguousarray(fr))
+    np.testing.assert_allclose(rl, np.rot90(gl, k=1), atol=1e-13)
+    np.testing.assert_allclose(rx, np.rot90(gy, k=1), atol=1e-13)
+
+
+def test_streaming_brute_force():
+    """A population leaving fluid node r along e_i lands on r + e_i; if that node is
+    solid it comes back to r with the opposite velocity (mid-link bounce-back)."""
+    rng = np.random.default_rng(5)
+    nx, ny = 7, 6
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[3, 2] = 1
+    solid[4, 5] = 1
+    post = rng.standard_normal((9, ny, nx))
+    nxt = oracle.stream(solid, post)
+    opp = [int(np.flatnonzero((E == -E[i]).all(1))[0]) for i in range(9)]
+    expect = np.zeros_like(post)
+    for y in range(ny):
+        for x in range(nx):
+            if solid[y, x]:
+                continue
+            for i in range(9):
+                xd, yd = (x + E[i, 0]) % nx, (y + E[i, 1]) % ny
+                if solid[yd, xd]:
+                    expect[opp[i], y, x] = post[i, y, x]
+                else:
+                    expect[i, yd, xd] = post[i, y, x]
+    np.testing.assert_array_equal(nxt, expect)
+
+
+def test_ghost_imposes_wall_gradient():
+    """At a flat wall the ghost value makes the central difference across the
+    wall plane equal to d_perp phi (pointing into the fluid)."""
+    rng = np.random.default_rng(8)
+    nx, ny = 9, 7
+    solid = wl.walls_mask(nx, ny)
+    phi = np.where(solid == 0, rng.uniform(-1, 1, (ny, nx)), 0.0)
+    dphi = np.where(solid != 0, rng.uniform(-0.4, 0.4, (ny, nx)), 0.0)
+    px = oracle.ghosts(solid, dphi, phi)
+    np.testing.assert_allclose(px[1] - px[0], dphi[0], atol=1e-15)          # bottom: into fluid = +y
+    np.testing.assert_allclose(px[ny - 2] - px[ny - 1], dphi[ny - 1], atol=1e-15)  # top: -y
+    np.testing.assert_array_equal(px[1:ny - 1], phi[1:ny - 1])
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_conservation_exact(collision):
+    """Sum rho and sum phi over fluid nodes are conserved by collision (f0/g0 closure,
+    S_00 = 0) and by streaming with bounce-back (a permutation)."""
+    p = wl.params(40, 24, 1.0, 0.6, collision)
+    inp = wl.random_fields(p, seed=21)
+    inp["dphi"] = wl.wall_field(inp["solid"], -0.2)
+    o = make_oracle(p, inp)
+    d0 = o.diagnostics()
+    o.step(300)
+    d1 = o.diagnostics()
+    assert abs(d1["sum_rho"] - d0["sum_rho"]) <= 1e-12 * d0["sum_rho"]
+    assert abs(d1["sum_phi"] - d0["sum_phi"]) <= 1e-12 * d0["n_fluid"]
+    assert np.isfinite(d1["kinetic"])
+
+
+def test_mrt_with_unit_rates_is_bgk_tau_one():
+    """With omega = 1 every non-conserved mode relaxes at rate 1, so MRT (Step 2 off)
+    equals BGK with tau = 1 (Eq. (mrtlb) with S = diag(0,1,1,0,1,0,1,1,1))."""
+    p = wl.params(30, 20, 1.0, 1.0, "bgk")
+    inp = wl.random_fields(p, seed=4)
+    inp["dphi"] = wl.wall_field(inp["solid"], 0.15)
+    a = make_oracle(p, inp)
+    b = make_oracle(p, inp, collision="mrt", zero_u_feq=0)
+    a.step(50)
+    b.step(50)
+    fa, ga = a.populations()
+    fb, gb = b.populations()
+    np.testing.assert_allclose(fb, fa, atol=1e-14)
+    np.testing.assert_allclose(gb, ga, atol=1e-14)
+
+
+def test_bgk_tau_one_is_local():
+    """For tau = 1 the population at r after one step is the equilibrium of node
+    r - e_i (Eq. (ss) with tau = 1), away from walls."""
+    p = wl.params(20, 16, 1.0, 1.0, "bgk")
+    inp = wl.random_fields(p, seed=9, walls=False)
+    o = make_oracle(p, inp)
+    o.step(3)
+    f, g = o.populations()
+    solid = inp["solid"]
+    rho, phi, ux, uy = oracle.moments(solid, f, g)
+    px = oracle.ghosts(solid, None, phi)
+    gx, gy, gl = oracle.gradients(px, solid)
+    P = orc_params(p)
+    ny, nx = solid.shape
+    feq = np.zeros((9, ny, nx))
+    geq = np.zeros((9, ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            feq[:, y, x], geq[:, y, x] = oracle.equilibria_node(
+                P, rho[y, x], phi[y, x], ux[y, x], uy[y, x], gx[y, x], gy[y, x], gl[y, x])
+    o.step(1)
+    f1, g1 = o.populations()
+    for i in range(9):
+        np.testing.assert_allclose(f1[i], np.roll(feq[i], shift=(E[i, 1], E[i, 0]), axis=(0, 1)),
+                                   atol=1e-14)
+        np.testing.assert_allclose(g1[i], np.roll(geq[i], shift=(E[i, 1], E[i, 0]), axis=(0, 1)),
+                                   atol=1e-14)
+
+
+def test_tau_interpolation():
+    """Eq. (tau): tau_beta at phi = -1, tau_alpha at phi = +1, linear between."""
+    P = oracle.make_params(4, 4, tau_alpha=3.0, tau_beta=0.7)
+    assert oracle.tau(P, 1.0) == pytest.approx(3.0)
+    assert oracle.tau(P, -1.0) == pytest.approx(0.7)
+    assert oracle.tau(P, 0.0) == pytest.approx(1.85)
+    assert (3.0 - 0.5) / (0.7 - 0.5) == pytest.approx(12.5)  # R_nu printed in Sec. IV
+
+
+def test_rejects_bad_parameters():
+    p = wl.params(10, 8, 1.0, 0.5, "bgk")
+    inp = wl.random_fields(p, seed=1)
+    with pytest.raises(ValueError):
+        make_oracle(p, inp)
+    p = wl.params(10, 8, 1.0, 1.0, "bgk")
+    inp = wl.random_fields(p, seed=1)
+    inp["phi0"][3, 3] = np.nan
+    with pytest.raises(ValueError):
+        make_oracle(p, inp)
