@@ -1,0 +1,227 @@
+/*
+ * lb.h - C ABI of the MI355X (gfx950) library for the binary free-energy
+ * lattice Boltzmann method of Pooley, Kusumaatmaja and Yeomans, "Contact line
+ * dynamics in binary lattice Boltzmann simulations" (arXiv:0812.1282).
+ *
+ * One call of lb_step advances a D2Q9 lattice by whole timesteps. Each
+ * timestep is one fused HIP sweep that, at every fluid node:
+ *   - pulls the post-collision populations f_i and g_i of the previous step
+ *     from the neighbours (Eqs. (stream1), (stream2)), bouncing back on solid
+ *     neighbours (mid-link bounce-back, Sec. IV and Sec. V.B);
+ *   - forms rho, phi and u (Eq. (moments));
+ *   - evaluates the isotropic gradient and Laplacian of phi (Appendix A,
+ *     Eq. (best)) from an LDS tile, with ghost values of phi at solid nodes
+ *     that impose the wall gradient d_perp phi = xi / kappa (Sec. II);
+ *   - forms mu = A phi + B phi^3 - kappa lap phi and p0 = rho/3 + A phi^2/2
+ *     + 3 B phi^4 / 4 (Eqs. (chempot), (p0); the paper's a is B = -A);
+ *   - forms tau(phi) (Eq. (tau)) and the equilibria of Appendix A, with u = 0
+ *     at boundary nodes when Step 2 of Sec. VI is enabled;
+ *   - collides f with BGK (Eq. (latbolt)) or MRT (Eqs. (mrtlb), (Matrix),
+ *     (diag)) and g with BGK (Eq. (gevo));
+ *   - writes the post-collision populations of the node.
+ *
+ * Conventions
+ *   - Node (x, y), 0 <= x < nx, 0 <= y < ny, has host index y*nx + x. The
+ *     lattice is periodic in x and y; walls are solid nodes of a mask.
+ *   - Velocities: e0 = (0,0), e1 = (1,0), e2 = (-1,0), e3 = (0,1), e4 = (0,-1),
+ *     e5 = (1,1), e6 = (-1,-1), e7 = (-1,1), e8 = (1,-1) (Sec. III.A).
+ *   - The state at step n is S_n: the post-streaming, pre-collision
+ *     populations. Host population arrays hold 9 planes of nx*ny values,
+ *     plane i first (index i*nx*ny + y*nx + x).
+ *   - d_perp points from the wall into the fluid, so d_perp phi < 0 makes the
+ *     phi > 0 phase wet the wall (contact angle below 90 degrees, measured
+ *     through the phi > 0 phase).
+ *
+ * Errors: every entry point returns LB_OK (0) or a negative LB_E* code and
+ * never throws; lb_last_error() returns the calling thread's last message.
+ * Host arrays passed in are borrowed for the duration of the call only.
+ * Asynchronous device failures surface at the next synchronising call.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)   /* invalid argument (sizes, tau <= 1/2, non-finite input, NULL) */
+#define LB_ENOMEM (-2)   /* device or host allocation failed, or a buffer is too small */
+#define LB_EHIP (-3)     /* a HIP runtime call failed */
+#define LB_ENUMERIC (-4) /* a diagnostic found a non-finite value */
+#define LB_ENODATA (-5)  /* a measurement found too few points / no wall intersection */
+#define LB_EIO (-6)      /* checkpoint file could not be written or read */
+
+/* Collision operator for f (g always uses BGK, Eq. (gevo)). */
+#define LB_BGK 0
+#define LB_MRT 1
+
+/* Storage of the populations in device memory. Arithmetic is FP64 for
+ * LB_F64 and FP32 for the others. LB_F16S / LB_BF16S store f_i minus a fixed
+ * rest-state value and g_1..g_8 in 16 bits, and g_0 in FP32. */
+#define LB_F64 0
+#define LB_F32 1
+#define LB_F16S 2
+#define LB_BF16S 3
+
+typedef struct lb_handle lb_handle;
+typedef struct lb_batch lb_batch;
+
+typedef struct {
+    int32_t nx, ny;       /* lattice size, each >= 3 */
+    double A, B;          /* Landau coefficients: mu = A phi + B phi^3 - kappa lap phi */
+    double kappa;         /* gradient-energy coefficient, Eq. (freeen) */
+    double Gamma;         /* mobility parameter of g^eq, Eq. (Mobility) */
+    double tau_alpha;     /* tau_rho in the phi = +1 phase, > 1/2 */
+    double tau_beta;      /* tau_rho in the phi = -1 phase, > 1/2 */
+    double tau_phi;       /* relaxation time of g, > 1/2 */
+    double rho_ref;       /* reference density of the 16-bit shifted storage */
+    int32_t collision;    /* LB_BGK or LB_MRT */
+    int32_t storage;      /* LB_F64, LB_F32, LB_F16S, LB_BF16S */
+    int32_t zero_u_feq;   /* Step 2 of Sec. VI: u = 0 at boundary nodes in f^eq */
+    int32_t zero_u_geq;   /* the same for g^eq */
+    int32_t diag_every;   /* enqueue the non-finite check every k steps (0 = never) */
+    int32_t reserved;     /* must be 0 */
+} lb_params;
+
+typedef struct {
+    double sum_rho;       /* FP64 sum of rho over fluid nodes of S_n */
+    double sum_phi;       /* FP64 sum of phi over fluid nodes */
+    double kinetic;       /* FP64 sum of rho |u|^2 / 2 */
+    double max_u;         /* max |u| */
+    int64_t n_fluid;      /* number of fluid nodes */
+    int64_t step;         /* n */
+} lb_diag;
+
+/* Tile shape of the sweep: block_x columns per workgroup (64, 128 or 256) and
+ * rows_per_block rows walked by each workgroup (1 .. 1024). */
+typedef struct {
+    int32_t block_x;
+    int32_t rows_per_block;
+} lb_tuning;
+
+/* Fill p with the defaults of the paper's Sec. IV set-up (a = kappa = 0.04,
+ * tau = 1, Gamma = 0.1, BGK, FP64, rho_ref = 1) for an nx x ny lattice. */
+int lb_default_params(int32_t nx, int32_t ny, lb_params* p);
+
+/* Bytes of device memory one lattice with these parameters needs, for a
+ * caller that provides its own buffer to lb_init_ext. */
+int lb_workspace_bytes(const lb_params* p, size_t* bytes);
+
+/*
+ * Create a lattice whose state S_0 is the equilibrium (Appendix A) of the
+ * initial fields, with the initial velocity in both f^eq and g^eq.
+ *   solid      nx*ny bytes, nonzero = solid node (required). A fluid node
+ *              whose eight neighbours are all solid is rejected.
+ *   wall_dphi  nx*ny values of d_perp phi, read at solid nodes (NULL = 0, a
+ *              neutral 90-degree wall).
+ *   phi0       nx*ny initial order parameter (required).
+ *   rho0, ux0, uy0  nx*ny (NULL = rho_ref, 0, 0). Values at solid nodes are
+ *              ignored.
+ *   stream     hipStream_t on which every kernel of this handle runs (NULL =
+ *              the null stream); borrowed, must outlive the handle.
+ * lb_init allocates the device memory itself; lb_init_ext uses a caller
+ * buffer of at least lb_workspace_bytes bytes (256-byte aligned) that must stay
+ * valid until lb_free. Errors: LB_EINVAL, LB_ENOMEM, LB_EHIP.
+ */
+int lb_init(const lb_params* p, const uint8_t* solid, const double* wall_dphi,
+            const double* phi0, const double* rho0, const double* ux0, const double* uy0,
+            void* stream, lb_handle** out);
+int lb_init_ext(const lb_params* p, const uint8_t* solid, const double* wall_dphi,
+                const double* phi0, const double* rho0, const double* ux0, const double* uy0,
+                void* stream, void* device_buffer, size_t buffer_bytes, lb_handle** out);
+
+/* Enqueue nsteps >= 0 timesteps on the handle's stream; does not block. */
+int lb_step(lb_handle* h, int64_t nsteps);
+
+/* Synchronise and copy the moments of S_n (Eq. (moments)) to host arrays of
+ * nx*ny doubles; any pointer may be NULL. Solid nodes read 0. */
+int lb_read_fields(lb_handle* h, double* phi, double* rho, double* ux, double* uy);
+
+/* Synchronise and copy S_n out: f and g, each 9*nx*ny doubles (NULL to skip).
+ * Solid nodes read 0. */
+int lb_read_populations(lb_handle* h, double* f, double* g);
+
+/* Synchronise; FP64 conservation sums and kinetic energy of S_n. Returns
+ * LB_ENUMERIC (with d filled) if any of them, or an earlier periodic check,
+ * is not finite. */
+int lb_diagnostics(lb_handle* h, lb_diag* d);
+
+/*
+ * Contact angle (Sec. IV): every axis link between two fluid nodes whose phi
+ * values have opposite signs gives the phi = 0 crossing by linear
+ * interpolation; crossings inside [x_lo, x_hi) x [y_lo, y_hi] (x and y taken at
+ * the periodic image nearest the window centre) are fitted by a least-squares
+ * circle in FP64, and the angle between the circle and the wall plane
+ * y = y_wall, whose normal into the fluid is (0, wall_dir) with wall_dir = +1
+ * or -1, is returned in degrees, measured through the phi > 0 phase. Outputs
+ * may be NULL except theta_deg. LB_ENODATA if fewer than 3 crossings are found
+ * or the circle does not reach the wall.
+ */
+int lb_contact_angle(lb_handle* h, double x_lo, double x_hi, double y_lo, double y_hi,
+                     double y_wall, int32_t wall_dir, double* theta_deg, double* xc,
+                     double* yc, double* radius, int64_t* n_points);
+
+/* Length of the phi > 0 column in a channel (Sec. VII): the FP64 sum of
+ * (1 + phi)/2 over fluid nodes with x_lo <= x < x_hi, divided by width. */
+int lb_fill_length(lb_handle* h, int32_t x_lo, int32_t x_hi, double width, double* length);
+
+/* Replace the wall gradient field (nx*ny, read at solid nodes; NULL = 0).
+ * Takes effect from the next enqueued step. */
+int lb_set_wall_dphi(lb_handle* h, const double* wall_dphi);
+
+/* Write / read a checkpoint: parameters, step count, mask, wall field and the
+ * device state, bit for bit. lb_load needs a handle of identical parameters. */
+int lb_save(lb_handle* h, const char* path);
+int lb_load(lb_handle* h, const char* path);
+
+/* Tile shape: set (lb_set_tuning), read (lb_get_tuning), or pick by timing
+ * candidate shapes on the handle's own stream with the state restored
+ * afterwards (lb_autotune). The choice never changes results. */
+int lb_set_tuning(lb_handle* h, const lb_tuning* t);
+int lb_get_tuning(lb_handle* h, lb_tuning* t);
+int lb_autotune(lb_handle* h, int32_t steps_per_trial, lb_tuning* chosen);
+
+/* Step count n of the current state. */
+int lb_get_step(lb_handle* h, int64_t* step);
+
+/* Release the handle and the device memory it allocated. NULL is a no-op. */
+int lb_free(lb_handle* h);
+
+/* Thread-local message of the last error (never NULL). */
+const char* lb_last_error(void);
+
+/* Eq. (theory) of Sec. IV: d_perp phi at the wall for an equilibrium contact
+ * angle theta (degrees, 0..180) with mu = A phi + B phi^3 - kappa lap phi,
+ * B = -A > 0. */
+int lb_dphi_for_angle(double theta_deg, double kappa, double A, double B, double* dphi);
+
+/*
+ * Batched ensembles: n independent lattices (own sizes, masks, parameters and
+ * initial fields) advanced together, one fused launch per timestep over the
+ * tiles of all members, replayed from a HIP graph. Every member must share
+ * storage, collision and the Step 2 flags; arrays are per member as in
+ * lb_init. lb_batch_step enqueues nsteps for every member.
+ */
+int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
+                  const double* const* wall_dphi, const double* const* phi0,
+                  const double* const* rho0, const double* const* ux0,
+                  const double* const* uy0, void* stream, const lb_tuning* tuning,
+                  lb_batch** out);
+int lb_batch_step(lb_batch* b, int64_t nsteps);
+int lb_batch_read_fields(lb_batch* b, int32_t member, double* phi, double* rho, double* ux,
+                         double* uy);
+int lb_batch_read_populations(lb_batch* b, int32_t member, double* f, double* g);
+int lb_batch_contact_angle(lb_batch* b, int32_t member, double x_lo, double x_hi,
+                           double y_lo, double y_hi, double y_wall, int32_t wall_dir,
+                           double* theta_deg);
+int lb_batch_get_tuning(lb_batch* b, lb_tuning* t);
+int lb_batch_free(lb_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_H */

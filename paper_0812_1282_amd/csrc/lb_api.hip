@@ -1,0 +1,1093 @@
+// Host side of the C ABI declared in include/lb.h.
+//
+// A "group" holds one or more lattices ("members") that advance together:
+// lb_handle is a group of one, lb_batch a group of n. Each member owns an
+// arena (see lb_internal.h) inside the group's device allocation; a batched
+// step is one launch over the tiles of every member.
+#include "lb.h"
+#include "lb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr int kEX[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
+constexpr int kEY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
+constexpr int kGraphSteps = 32;  // timesteps per captured graph (even: parity returns)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+namespace lbm {
+
+Layout make_layout(int nx, int ny, int storage) {
+    Layout L{};
+    L.pitch = (int32_t)round_up((size_t)nx, kPitchAlign);
+    L.plane = (int64_t)L.pitch * ny;
+    const size_t plane = (size_t)L.plane;
+    if (storage == ST_F64) {
+        L.buf_bytes = round_up(18 * plane * 8, 256);
+    } else if (storage == ST_F32) {
+        L.buf_bytes = round_up(18 * plane * 4, 256);
+    } else {
+        L.g0_offset = round_up(17 * plane * 2, 256);
+        L.buf_bytes = round_up(L.g0_offset + plane * 4, 256);
+    }
+    const size_t dsz = storage == ST_F64 ? 8 : 4;
+    L.off_buf0 = 0;
+    L.off_buf1 = L.buf_bytes;
+    L.off_nbr = 2 * L.buf_bytes;
+    L.off_grec = L.off_nbr + round_up(plane, 256);
+    L.off_dphi = L.off_grec + round_up(plane, 256);
+    L.off_misc = L.off_dphi + round_up(plane * dsz, 256);
+    const size_t tiles_max = ((size_t)(nx + 63) / 64) * (size_t)ny;
+    const size_t node_blocks = ((size_t)nx * ny + 255) / 256;
+    L.n_partials = std::max(tiles_max, node_blocks) + 1;
+    L.n_tiles_max = tiles_max;
+    L.off_partials = L.off_misc;
+    L.off_diag = L.off_partials + round_up(L.n_partials * kPartials * 8, 256);
+    L.off_flag = L.off_diag + 256;
+    L.off_counter = L.off_flag + 256;
+    L.off_view = L.off_counter + 256;
+    L.off_tiles = L.off_view + round_up(sizeof(View), 256);
+    L.total = L.off_tiles;
+    return L;
+}
+
+}  // namespace lbm
+
+struct Member {
+    lb_params p;
+    Layout L;
+    char* base = nullptr;  // arena
+    View view{};
+    View* d_view = nullptr;
+    std::vector<uint8_t> solid;  // host copy (nx*ny)
+    std::vector<double> dphi;    // host copy (nx*ny)
+    int64_t n_fluid = 0;
+};
+
+struct Group {
+    std::vector<Member> m;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    char* alloc = nullptr;  // owned device memory (null for caller buffers)
+    int parity = 0;
+    int64_t step = 0;
+    int block_x = 256;
+    int rows = 32;
+    // batched launch data (members > 1)
+    Tile* d_tiles = nullptr;
+    int32_t* d_first = nullptr;  // n+1 tile offsets per member
+    double* d_partials = nullptr;
+    double* d_diag = nullptr;
+    int32_t* d_flag = nullptr;
+    View* d_views = nullptr;
+    int n_tiles = 0;
+    char* batch_alloc = nullptr;
+    // cached graphs keyed by whether the graph carries the periodic check
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool batched = false;
+};
+
+struct lb_handle {
+    Group g;
+};
+struct lb_batch {
+    Group g;
+};
+
+namespace {
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int validate_params(const lb_params* p) {
+    if (!p) return fail(LB_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(LB_EINVAL, "nx and ny must be >= 3");
+    if (p->nx > (1 << 24) || p->ny > (1 << 24) || (int64_t)p->nx * p->ny > (int64_t)1 << 34)
+        return fail(LB_EINVAL, "lattice too large");
+    const double vals[] = {p->A, p->B, p->kappa, p->Gamma, p->tau_alpha,
+                           p->tau_beta, p->tau_phi, p->rho_ref};
+    for (double v : vals)
+        if (!is_finite(v)) return fail(LB_EINVAL, "non-finite parameter");
+    if (!(p->tau_alpha > 0.5) || !(p->tau_beta > 0.5) || !(p->tau_phi > 0.5))
+        return fail(LB_EINVAL, "tau_alpha, tau_beta and tau_phi must exceed 1/2");
+    if (!(p->rho_ref > 0)) return fail(LB_EINVAL, "rho_ref must be positive");
+    if (p->collision != LB_BGK && p->collision != LB_MRT)
+        return fail(LB_EINVAL, "collision must be LB_BGK or LB_MRT");
+    if (p->storage < LB_F64 || p->storage > LB_BF16S)
+        return fail(LB_EINVAL, "unknown storage format");
+    if ((p->zero_u_feq != 0 && p->zero_u_feq != 1) || (p->zero_u_geq != 0 && p->zero_u_geq != 1))
+        return fail(LB_EINVAL, "zero_u flags must be 0 or 1");
+    if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
+    if (p->reserved != 0) return fail(LB_EINVAL, "reserved must be 0");
+    return LB_OK;
+}
+
+int validate_inputs(const lb_params* p, const uint8_t* solid, const double* dphi,
+                    const double* phi0, const double* rho0, const double* ux0, const double* uy0,
+                    int64_t* n_fluid) {
+    if (!solid || !phi0) return fail(LB_EINVAL, "solid and phi0 are required");
+    const int nx = p->nx, ny = p->ny;
+    int64_t nf = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int64_t h = (int64_t)y * nx + x;
+            if (solid[h]) {
+                if (dphi && !is_finite(dphi[h])) return fail(LB_EINVAL, "non-finite wall_dphi");
+                continue;
+            }
+            ++nf;
+            if (!is_finite(phi0[h])) return fail(LB_EINVAL, "non-finite phi0");
+            if (rho0 && !(is_finite(rho0[h]) && rho0[h] > 0))
+                return fail(LB_EINVAL, "rho0 must be finite and positive at fluid nodes");
+            if ((ux0 && !is_finite(ux0[h])) || (uy0 && !is_finite(uy0[h])))
+                return fail(LB_EINVAL, "non-finite initial velocity");
+            bool enclosed = true;
+            for (int i = 1; i < 9; ++i) {
+                const int xs = (x + kEX[i] + nx) % nx, ys = (y + kEY[i] + ny) % ny;
+                if (!solid[(int64_t)ys * nx + xs]) enclosed = false;
+            }
+            if (enclosed) return fail(LB_EINVAL, "a fluid node has no fluid neighbour");
+        }
+    *n_fluid = nf;
+    return LB_OK;
+}
+
+std::vector<uint8_t> make_nbr(const lb_params* p, const Layout& L, const uint8_t* solid) {
+    const int nx = p->nx, ny = p->ny;
+    std::vector<uint8_t> nbr((size_t)L.plane, 0xFF);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int64_t h = (int64_t)y * nx + x;
+            uint8_t b = 0xFF;
+            if (!solid[h]) {
+                b = 0;
+                for (int i = 1; i < 9; ++i) {
+                    const int xs = (x - kEX[i] + nx) % nx, ys = (y - kEY[i] + ny) % ny;
+                    if (solid[(int64_t)ys * nx + xs]) b |= (uint8_t)(1u << (i - 1));
+                }
+            }
+            nbr[(size_t)y * L.pitch + x] = b;
+        }
+    return nbr;
+}
+
+std::vector<uint8_t> make_grec(const lb_params* p, const Layout& L, const uint8_t* solid) {
+    const int nx = p->nx, ny = p->ny;
+    std::vector<uint8_t> grec((size_t)L.plane, 0);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (!solid[(int64_t)y * nx + x]) continue;
+            uint8_t b = 0;
+            for (int m = 1; m < 9; ++m) {
+                const int xs = (x + kEX[m] + nx) % nx, ys = (y + kEY[m] + ny) % ny;
+                if (!solid[(int64_t)ys * nx + xs]) b |= (uint8_t)(1u << (m - 1));
+            }
+            grec[(size_t)y * L.pitch + x] = b;
+        }
+    return grec;
+}
+
+int upload_dphi(Member& mb, const double* dphi, hipStream_t st) {
+    const lb_params& p = mb.p;
+    const Layout& L = mb.L;
+    mb.dphi.assign((size_t)p.nx * p.ny, 0.0);
+    for (int64_t h = 0; h < (int64_t)p.nx * p.ny; ++h)
+        if (mb.solid[h] && dphi) mb.dphi[h] = dphi[h];
+    char* dst = mb.base + L.off_dphi;
+    if (p.storage == LB_F64) {
+        std::vector<double> d((size_t)L.plane, 0.0);
+        for (int y = 0; y < p.ny; ++y)
+            for (int x = 0; x < p.nx; ++x) d[(size_t)y * L.pitch + x] = mb.dphi[(size_t)y * p.nx + x];
+        HIPCHK(hipMemcpyAsync(dst, d.data(), d.size() * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        std::vector<float> d((size_t)L.plane, 0.0f);
+        for (int y = 0; y < p.ny; ++y)
+            for (int x = 0; x < p.nx; ++x)
+                d[(size_t)y * L.pitch + x] = (float)mb.dphi[(size_t)y * p.nx + x];
+        HIPCHK(hipMemcpyAsync(dst, d.data(), d.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return LB_OK;
+}
+
+// Initialise one member whose arena base is already set.
+int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const double* dphi,
+                const double* phi0, const double* rho0, const double* ux0, const double* uy0,
+                hipStream_t st) {
+    mb.p = *p;
+    const Layout& L = mb.L;
+    const int nx = p->nx, ny = p->ny;
+    const size_t n = (size_t)nx * ny;
+    HIPCHK(launch_fill(mb.base, 0, L.total, st));
+    mb.solid.assign(solid, solid + n);
+    for (auto& s : mb.solid) s = s ? 1 : 0;
+    const std::vector<uint8_t> nbr = make_nbr(p, L, mb.solid.data());
+    const std::vector<uint8_t> grec = make_grec(p, L, mb.solid.data());
+    HIPCHK(hipMemcpyAsync(mb.base + L.off_nbr, nbr.data(), nbr.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(mb.base + L.off_grec, grec.data(), grec.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int rc = upload_dphi(mb, dphi, st);
+    if (rc) return rc;
+
+    View& v = mb.view;
+    v = View{};
+    v.nx = nx;
+    v.ny = ny;
+    v.pitch = L.pitch;
+    v.plane = L.plane;
+    v.g0_offset = (int64_t)L.g0_offset;
+    v.buf[0] = mb.base + L.off_buf0;
+    v.buf[1] = mb.base + L.off_buf1;
+    v.nbr = reinterpret_cast<const uint8_t*>(mb.base + L.off_nbr);
+    v.grec = reinterpret_cast<const uint8_t*>(mb.base + L.off_grec);
+    v.dphi = mb.base + L.off_dphi;
+    v.A = p->A;
+    v.B = p->B;
+    v.kappa = p->kappa;
+    v.Gamma = p->Gamma;
+    v.tau_alpha = p->tau_alpha;
+    v.tau_beta = p->tau_beta;
+    v.inv_tau_phi = 1.0 / p->tau_phi;
+    // Rest state of the model at rho_ref in either bulk phase (p0 is even in
+    // phi): f_i = w_i p0 for i >= 1 and f_0 = rho_ref - (5/3) p0.
+    const double p0 = p->rho_ref / 3.0 + 0.5 * p->A + 0.75 * p->B;
+    for (int i = 1; i < 9; ++i) v.ref[i] = (float)((i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * p0);
+    v.ref[0] = (float)(p->rho_ref - 5.0 / 3.0 * p0);
+    if (p->storage == LB_F64 || p->storage == LB_F32)
+        for (int i = 0; i < 9; ++i) v.ref[i] = 0.0f;
+    v.zero_u_feq = p->zero_u_feq;
+    v.zero_u_geq = p->zero_u_geq;
+    v.storage = p->storage;
+    v.collision = p->collision;
+    mb.d_view = reinterpret_cast<View*>(mb.base + L.off_view);
+    HIPCHK(hipMemcpyAsync(mb.d_view, &v, sizeof(View), hipMemcpyHostToDevice, st));
+
+    // Stage the initial fields (compact FP64, defaults filled) in buf[1].
+    std::vector<double> stage(4 * n);
+    for (size_t h = 0; h < n; ++h) {
+        stage[h] = mb.solid[h] ? 0.0 : phi0[h];
+        stage[n + h] = rho0 ? rho0[h] : p->rho_ref;
+        stage[2 * n + h] = ux0 ? ux0[h] : 0.0;
+        stage[3 * n + h] = uy0 ? uy0[h] : 0.0;
+    }
+    double* d_stage = reinterpret_cast<double*>(v.buf[1]);
+    HIPCHK(hipMemcpyAsync(d_stage, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_init_state(v, d_stage, d_stage + n, d_stage + 2 * n, d_stage + 3 * n, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LB_OK;
+}
+
+void destroy_graphs(Group& g) {
+    for (auto& e : g.graph)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+}
+
+int check_tuning(int bx, int rows) {
+    if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "block_x must be 64, 128 or 256");
+    if (rows < 1 || rows > 1024) return fail(LB_EINVAL, "rows_per_block must be in 1..1024");
+    return LB_OK;
+}
+
+// Tile table of a batched group for the current tuning.
+int build_tiles(Group& g) {
+    std::vector<Tile> tiles;
+    std::vector<int32_t> first;
+    for (size_t k = 0; k < g.m.size(); ++k) {
+        const lb_params& p = g.m[k].p;
+        first.push_back((int32_t)tiles.size());
+        const int tx = (p.nx + g.block_x - 1) / g.block_x;
+        const int ty = (p.ny + g.rows - 1) / g.rows;
+        for (int j = 0; j < ty; ++j)
+            for (int i = 0; i < tx; ++i) tiles.push_back(Tile{(int32_t)k, i, j, first.back()});
+    }
+    first.push_back((int32_t)tiles.size());
+    if (tiles.size() > (size_t)g.n_tiles)
+        return fail(LB_EINVAL, "tile table too small for this tuning");
+    HIPCHK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                          hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.d_first, first.data(), first.size() * 4, hipMemcpyHostToDevice,
+                          g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    return LB_OK;
+}
+
+int current_tiles(const Group& g) {
+    int n = 0;
+    for (const auto& mb : g.m)
+        n += ((mb.p.nx + g.block_x - 1) / g.block_x) * ((mb.p.ny + g.rows - 1) / g.rows);
+    return n;
+}
+
+// Enqueue one timestep of every member on stream st.
+hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
+    const Member& m0 = g.m[0];
+    if (!g.batched) {
+        const Layout& L = m0.L;
+        const int gx = (m0.p.nx + g.block_x - 1) / g.block_x;
+        const int gy = (m0.p.ny + g.rows - 1) / g.rows;
+        double* partials = reinterpret_cast<double*>(m0.base + L.off_partials);
+        hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag, m0.d_view,
+                                    nullptr, 0, gx, gy, g.rows, parity, partials, st);
+        if (e != hipSuccess || !diag) return e;
+        return launch_finalize(nullptr, nullptr, 1, gx * gy, partials,
+                               reinterpret_cast<double*>(m0.base + L.off_diag),
+                               reinterpret_cast<int32_t*>(m0.base + L.off_flag), st);
+    }
+    const int nt = current_tiles(g);
+    hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag, g.d_views,
+                                g.d_tiles, nt, 0, 0, g.rows, parity, g.d_partials, st);
+    if (e != hipSuccess || !diag) return e;
+    return launch_finalize(g.d_tiles, g.d_first, (int)g.m.size(), 0, g.d_partials, g.d_diag,
+                           g.d_flag, st);
+}
+
+int group_step(Group& g, int64_t nsteps) {
+    if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+    const int de = g.m[0].p.diag_every;
+    auto is_diag = [&](int64_t s) { return de > 0 && s % de == 0; };
+    int64_t left = nsteps;
+    while (left > 0) {
+        const bool graph_ok = left >= kGraphSteps && g.parity == 0 &&
+                              (de == 0 || (kGraphSteps % de == 0 && g.step % de == 0));
+        if (graph_ok) {
+            const int key = de > 0 ? 1 : 0;
+            if (!g.graph[key]) {
+                if (!g.capture_stream)
+                    HIPCHK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
+                HIPCHK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
+                hipError_t ce = hipSuccess;
+                for (int s = 0; s < kGraphSteps && ce == hipSuccess; ++s)
+                    ce = enqueue_one(g, de > 0 && s % de == 0, s & 1, g.capture_stream);
+                hipGraph_t graph = nullptr;
+                hipError_t ee = hipStreamEndCapture(g.capture_stream, &graph);
+                if (ce != hipSuccess || ee != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return fail(LB_EHIP, std::string("graph capture failed: ") +
+                                             hipGetErrorString(ce != hipSuccess ? ce : ee));
+                }
+                hipError_t ie = hipGraphInstantiate(&g.graph[key], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ie != hipSuccess)
+                    return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            HIPCHK(hipGraphLaunch(g.graph[key], g.stream));
+            g.step += kGraphSteps;
+            left -= kGraphSteps;
+            continue;
+        }
+        HIPCHK(enqueue_one(g, is_diag(g.step), g.parity, g.stream));
+        g.parity ^= 1;
+        g.step += 1;
+        left -= 1;
+    }
+    return LB_OK;
+}
+
+int check_flag(Group& g) {
+    for (size_t k = 0; k < g.m.size(); ++k) {
+        int32_t flag = 0;
+        const int32_t* src = g.batched ? g.d_flag + k
+                                       : reinterpret_cast<const int32_t*>(g.m[k].base + g.m[k].L.off_flag);
+        HIPCHK(hipMemcpyAsync(&flag, src, 4, hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        if (flag) return fail(LB_ENUMERIC, "a periodic diagnostic found a non-finite value");
+    }
+    return LB_OK;
+}
+
+int read_fields(Group& g, int k, double* phi, double* rho, double* ux, double* uy) {
+    Member& mb = g.m[k];
+    const size_t n = (size_t)mb.p.nx * mb.p.ny;
+    double* scratch = reinterpret_cast<double*>(mb.view.buf[g.parity ^ 1]);
+    HIPCHK(launch_moments(mb.view, g.parity, scratch, nullptr, 0, 0, 0, g.stream));
+    double* outs[4] = {phi, rho, ux, uy};
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            HIPCHK(hipMemcpyAsync(outs[q], scratch + q * n, n * 8, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    return LB_OK;
+}
+
+int read_populations(Group& g, int k, double* f, double* gg) {
+    Member& mb = g.m[k];
+    const size_t n = (size_t)mb.p.nx * mb.p.ny;
+    double* scratch = reinterpret_cast<double*>(mb.view.buf[g.parity ^ 1]);
+    for (int pl = 0; pl < 18; ++pl) {
+        double* out = pl < 9 ? f : gg;
+        if (!out) continue;
+        HIPCHK(launch_read_plane(mb.view, g.parity, pl, scratch, g.stream));
+        HIPCHK(hipMemcpyAsync(out + (size_t)(pl % 9) * n, scratch, n * 8, hipMemcpyDeviceToHost,
+                              g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+    }
+    return LB_OK;
+}
+
+// Sums over fluid nodes: out[0..5] = sum rho, sum phi, kinetic, max |u|, count,
+// sum (1+phi)/2 for x_lo <= x < x_hi.
+int reduce_member(Group& g, int k, int32_t x_lo, int32_t x_hi, double out[6]) {
+    Member& mb = g.m[k];
+    const Layout& L = mb.L;
+    double* partials = reinterpret_cast<double*>(mb.base + L.off_partials);
+    double* diag = reinterpret_cast<double*>(mb.base + L.off_diag);
+    int32_t* flag = reinterpret_cast<int32_t*>(mb.base + L.off_flag);
+    const int nrec = (int)(((int64_t)mb.p.nx * mb.p.ny + 255) / 256);
+    HIPCHK(launch_moments(mb.view, g.parity, nullptr, partials, (int)L.n_partials, x_lo, x_hi,
+                          g.stream));
+    // A separate scratch flag keeps the sticky periodic flag untouched.
+    HIPCHK(launch_finalize(nullptr, nullptr, 1, nrec, partials, diag, flag + 1, g.stream));
+    double rec[kPartials];
+    HIPCHK(hipMemcpyAsync(rec, diag, sizeof(rec), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    for (int q = 0; q < 6; ++q) out[q] = rec[q];
+    return LB_OK;
+}
+
+// Kasa circle fit of the crossings, in FP64 on the host after sorting by link,
+// so the result does not depend on the order in which the GPU found them.
+int contact_angle(Group& g, int k, double x_lo, double x_hi, double y_lo, double y_hi,
+                  double y_wall, int wall_dir, double* theta, double* xc_out, double* yc_out,
+                  double* r_out, int64_t* np_out) {
+    if (!theta) return fail(LB_EINVAL, "theta_deg is NULL");
+    if (wall_dir != 1 && wall_dir != -1) return fail(LB_EINVAL, "wall_dir must be +1 or -1");
+    if (!(x_hi > x_lo) || !(y_hi >= y_lo)) return fail(LB_EINVAL, "empty window");
+    Member& mb = g.m[k];
+    const int nx = mb.p.nx, ny = mb.p.ny;
+    const Layout& L = mb.L;
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(mb.base + L.off_counter);
+    void* pts = mb.view.buf[g.parity ^ 1];
+    const int64_t cap = (int64_t)(L.buf_bytes / sizeof(Crossing));
+    HIPCHK(launch_fill(counter, 0, 8, g.stream));
+    HIPCHK(launch_crossings(mb.view, g.parity, pts, cap, counter, g.stream));
+    unsigned long long count = 0;
+    HIPCHK(hipMemcpyAsync(&count, counter, 8, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    if ((int64_t)count > cap) return fail(LB_ENOMEM, "too many interface crossings");
+    std::vector<Crossing> c(count);
+    if (count) {
+        HIPCHK(hipMemcpyAsync(c.data(), pts, count * sizeof(Crossing), hipMemcpyDeviceToHost,
+                              g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+    }
+    std::sort(c.begin(), c.end(), [](const Crossing& a, const Crossing& b) { return a.key < b.key; });
+    const double cx = 0.5 * (x_lo + x_hi), cy = 0.5 * (y_lo + y_hi);
+    std::vector<double> px, py, ex, ey;
+    for (const Crossing& q : c) {
+        const uint64_t node = q.key >> 2;
+        const int axis = (int)((q.key >> 1) & 1);
+        const bool base_pos = q.key & 1;
+        const double bx = (double)(node % (uint64_t)nx), by = (double)(node / (uint64_t)nx);
+        double x = bx + (axis == 0 ? q.t : 0.0), y = by + (axis == 1 ? q.t : 0.0);
+        double qx = base_pos ? bx : bx + (axis == 0), qy = base_pos ? by : by + (axis == 1);
+        const double sx = nx * std::nearbyint((x - cx) / nx);
+        const double sy = ny * std::nearbyint((y - cy) / ny);
+        x -= sx; qx -= sx;
+        y -= sy; qy -= sy;
+        if (x >= x_lo && x < x_hi && y >= y_lo && y <= y_hi) {
+            px.push_back(x); py.push_back(y); ex.push_back(qx); ey.push_back(qy);
+        }
+    }
+    const size_t m = px.size();
+    if (np_out) *np_out = (int64_t)m;
+    if (m < 3) return fail(LB_ENODATA, "fewer than 3 interface crossings in the window");
+    // Normal equations of x^2 + y^2 + D x + E y + F = 0 in coordinates centred on the mean.
+    double mx = 0, my = 0;
+    for (size_t i = 0; i < m; ++i) { mx += px[i]; my += py[i]; }
+    mx /= m; my /= m;
+    double S[3][4] = {{0}};
+    for (size_t i = 0; i < m; ++i) {
+        const double a[3] = {px[i] - mx, py[i] - my, 1.0};
+        const double z = -(a[0] * a[0] + a[1] * a[1]);
+        for (int r = 0; r < 3; ++r) {
+            for (int s = 0; s < 3; ++s) S[r][s] += a[r] * a[s];
+            S[r][3] += a[r] * z;
+        }
+    }
+    for (int col = 0; col < 3; ++col) {  // Gaussian elimination, partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r) if (std::fabs(S[r][col]) > std::fabs(S[piv][col])) piv = r;
+        if (S[piv][col] == 0.0) return fail(LB_ENODATA, "degenerate crossing set (collinear)");
+        for (int s = 0; s < 4; ++s) std::swap(S[col][s], S[piv][s]);
+        for (int r = 0; r < 3; ++r) {
+            if (r == col) continue;
+            const double fct = S[r][col] / S[col][col];
+            for (int s = col; s < 4; ++s) S[r][s] -= fct * S[col][s];
+        }
+    }
+    const double D = S[0][3] / S[0][0], E = S[1][3] / S[1][1], F = S[2][3] / S[2][2];
+    const double xc = mx - D / 2, yc = my - E / 2;
+    const double r2 = D * D / 4 + E * E / 4 - F;
+    if (!(r2 > 0)) return fail(LB_ENODATA, "circle fit failed");
+    const double R = std::sqrt(r2);
+    if (xc_out) *xc_out = xc;
+    if (yc_out) *yc_out = yc;
+    if (r_out) *r_out = R;
+    if (std::fabs(yc - y_wall) > R) return fail(LB_ENODATA, "fitted circle does not reach the wall");
+    size_t inside = 0;
+    for (size_t i = 0; i < m; ++i)
+        if (std::hypot(ex[i] - xc, ey[i] - yc) < R) ++inside;
+    double cosv = -wall_dir * (yc - y_wall) / R;
+    cosv = std::max(-1.0, std::min(1.0, cosv));
+    double th = std::acos(cosv) * 180.0 / M_PI;
+    if (!(2 * inside > m)) th = 180.0 - th;
+    *theta = th;
+    return LB_OK;
+}
+
+int alloc_group_single(Group& g, const lb_params* p, void* ext, size_t ext_bytes) {
+    g.m.resize(1);
+    Member& mb = g.m[0];
+    mb.L = make_layout(p->nx, p->ny, p->storage);
+    if (ext) {
+        if (ext_bytes < mb.L.total) return fail(LB_ENOMEM, "device buffer smaller than lb_workspace_bytes");
+        if (reinterpret_cast<uintptr_t>(ext) % 256) return fail(LB_EINVAL, "device buffer must be 256-byte aligned");
+        mb.base = reinterpret_cast<char*>(ext);
+    } else {
+        hipError_t e = hipMalloc(&g.alloc, mb.L.total);
+        if (e != hipSuccess) {
+            g.alloc = nullptr;
+            return fail(LB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        mb.base = g.alloc;
+    }
+    return LB_OK;
+}
+
+void free_group(Group& g) {
+    if (g.stream) (void)hipStreamSynchronize(g.stream);
+    destroy_graphs(g);
+    if (g.capture_stream) (void)hipStreamDestroy(g.capture_stream);
+    if (g.alloc) (void)hipFree(g.alloc);
+    if (g.batch_alloc) (void)hipFree(g.batch_alloc);
+    g.alloc = nullptr;
+    g.batch_alloc = nullptr;
+}
+
+int init_single(const lb_params* p, const uint8_t* solid, const double* dphi, const double* phi0,
+                const double* rho0, const double* ux0, const double* uy0, void* stream, void* ext,
+                size_t ext_bytes, lb_handle** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_params(p);
+    if (rc) return rc;
+    int64_t nf = 0;
+    rc = validate_inputs(p, solid, dphi, phi0, rho0, ux0, uy0, &nf);
+    if (rc) return rc;
+    lb_handle* h = new lb_handle();
+    Group& g = h->g;
+    g.stream = reinterpret_cast<hipStream_t>(stream);
+    g.block_x = 256;
+    g.rows = 32;
+    rc = alloc_group_single(g, p, ext, ext_bytes);
+    if (!rc) rc = init_member(g.m[0], p, solid, dphi, phi0, rho0, ux0, uy0, g.stream);
+    if (rc) {
+        const std::string msg = g_err;
+        free_group(g);
+        delete h;
+        return fail(rc, msg);
+    }
+    g.m[0].n_fluid = nf;
+    *out = h;
+    return LB_OK;
+}
+
+// Save the state buffer, run `fn`, restore the state, step and parity.
+template <class Fn>
+int with_restored_state(Group& g, Fn fn) {
+    std::vector<std::vector<char>> host;
+    HIPCHK(hipStreamSynchronize(g.stream));
+    for (auto& mb : g.m) {
+        host.emplace_back(mb.L.buf_bytes);
+        HIPCHK(hipMemcpy(host.back().data(), mb.view.buf[g.parity], mb.L.buf_bytes,
+                         hipMemcpyDeviceToHost));
+    }
+    const int par = g.parity;
+    const int64_t step = g.step;
+    int rc = fn();
+    HIPCHK(hipStreamSynchronize(g.stream));
+    for (size_t k = 0; k < g.m.size(); ++k)
+        HIPCHK(hipMemcpy(g.m[k].view.buf[par], host[k].data(), g.m[k].L.buf_bytes,
+                         hipMemcpyHostToDevice));
+    g.parity = par;
+    g.step = step;
+    return rc;
+}
+
+int set_tuning(Group& g, int bx, int rows) {
+    int rc = check_tuning(bx, rows);
+    if (rc) return rc;
+    if (g.batched) {
+        const int old_bx = g.block_x, old_rows = g.rows;
+        g.block_x = bx;
+        g.rows = rows;
+        if (current_tiles(g) > g.n_tiles) {
+            g.block_x = old_bx;
+            g.rows = old_rows;
+            return fail(LB_EINVAL, "tuning needs more tiles than were allocated");
+        }
+        destroy_graphs(g);
+        return build_tiles(g);
+    }
+    g.block_x = bx;
+    g.rows = rows;
+    destroy_graphs(g);
+    return LB_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
+
+int autotune(Group& g, int steps, lb_tuning* chosen) {
+    if (steps < 1) return fail(LB_EINVAL, "steps_per_trial must be >= 1");
+    int max_ny = 0, total = 0;
+    for (auto& mb : g.m) { max_ny = std::max(max_ny, mb.p.ny); total += mb.p.nx * mb.p.ny; }
+    const auto key = std::make_tuple(g.m[0].p.nx, max_ny, g.m[0].p.storage, g.m[0].p.collision,
+                                     g.batched ? total : -1);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            int rc = set_tuning(g, it->second.first, it->second.second);
+            if (chosen) *chosen = lb_tuning{g.block_x, g.rows};
+            return rc;
+        }
+    }
+    const int cand_bx[] = {64, 128, 256};
+    const int cand_rows[] = {8, 16, 32, 64, 128};
+    int best_bx = g.block_x, best_rows = g.rows;
+    float best = 1e30f;
+    const int diag_save = g.m[0].p.diag_every;
+    int rc = with_restored_state(g, [&]() -> int {
+        for (auto& mb : g.m) mb.p.diag_every = 0;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (int bx : cand_bx)
+            for (int rows : cand_rows) {
+                if (rows > 2 * max_ny) continue;
+                if (set_tuning(g, bx, rows)) continue;
+                for (int s = 0; s < 2; ++s)
+                    HIPCHK(enqueue_one(g, false, (g.parity + s) & 1, g.stream));
+                HIPCHK(hipEventRecord(e0, g.stream));
+                for (int s = 0; s < steps; ++s)
+                    HIPCHK(enqueue_one(g, false, (g.parity + s) & 1, g.stream));
+                HIPCHK(hipEventRecord(e1, g.stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; best_bx = bx; best_rows = rows; }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return LB_OK;
+    });
+    for (auto& mb : g.m) mb.p.diag_every = diag_save;
+    if (rc) return rc;
+    rc = set_tuning(g, best_bx, best_rows);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best_bx, best_rows};
+    }
+    if (chosen) *chosen = lb_tuning{g.block_x, g.rows};
+    return LB_OK;
+}
+
+struct CkptHeader {
+    char magic[8];
+    int32_t version;
+    int32_t parity;
+    int64_t step;
+    lb_params params;
+    uint64_t buf_bytes;
+    uint64_t n;
+};
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int lb_default_params(int32_t nx, int32_t ny, lb_params* p) {
+    if (!p) return fail(LB_EINVAL, "params is NULL");
+    *p = lb_params{};
+    p->nx = nx;
+    p->ny = ny;
+    p->A = -0.04;
+    p->B = 0.04;
+    p->kappa = 0.04;
+    p->Gamma = 0.1;
+    p->tau_alpha = 1.0;
+    p->tau_beta = 1.0;
+    p->tau_phi = 1.0;
+    p->rho_ref = 1.0;
+    p->collision = LB_BGK;
+    p->storage = LB_F64;
+    return LB_OK;
+}
+
+int lb_workspace_bytes(const lb_params* p, size_t* bytes) {
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if (!bytes) return fail(LB_EINVAL, "bytes is NULL");
+    *bytes = make_layout(p->nx, p->ny, p->storage).total;
+    return LB_OK;
+}
+
+int lb_init(const lb_params* p, const uint8_t* solid, const double* wall_dphi, const double* phi0,
+            const double* rho0, const double* ux0, const double* uy0, void* stream,
+            lb_handle** out) {
+    return init_single(p, solid, wall_dphi, phi0, rho0, ux0, uy0, stream, nullptr, 0, out);
+}
+
+int lb_init_ext(const lb_params* p, const uint8_t* solid, const double* wall_dphi,
+                const double* phi0, const double* rho0, const double* ux0, const double* uy0,
+                void* stream, void* device_buffer, size_t buffer_bytes, lb_handle** out) {
+    if (!device_buffer) return fail(LB_EINVAL, "device_buffer is NULL");
+    return init_single(p, solid, wall_dphi, phi0, rho0, ux0, uy0, stream, device_buffer,
+                       buffer_bytes, out);
+}
+
+int lb_step(lb_handle* h, int64_t nsteps) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return group_step(h->g, nsteps);
+}
+
+int lb_get_step(lb_handle* h, int64_t* step) {
+    if (!h || !step) return fail(LB_EINVAL, "NULL argument");
+    *step = h->g.step;
+    return LB_OK;
+}
+
+int lb_read_fields(lb_handle* h, double* phi, double* rho, double* ux, double* uy) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    int rc = read_fields(h->g, 0, phi, rho, ux, uy);
+    if (rc) return rc;
+    return check_flag(h->g);
+}
+
+int lb_read_populations(lb_handle* h, double* f, double* g) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return read_populations(h->g, 0, f, g);
+}
+
+int lb_diagnostics(lb_handle* h, lb_diag* d) {
+    if (!h || !d) return fail(LB_EINVAL, "NULL argument");
+    double s[6];
+    int rc = reduce_member(h->g, 0, 0, 0, s);
+    if (rc) return rc;
+    d->sum_rho = s[0];
+    d->sum_phi = s[1];
+    d->kinetic = s[2];
+    d->max_u = s[3];
+    d->n_fluid = (int64_t)std::llround(s[4]);
+    d->step = h->g.step;
+    if (!is_finite(s[0]) || !is_finite(s[1]) || !is_finite(s[2]) || !(s[3] == s[3]))
+        return fail(LB_ENUMERIC, "non-finite conservation sums");
+    return check_flag(h->g);
+}
+
+int lb_contact_angle(lb_handle* h, double x_lo, double x_hi, double y_lo, double y_hi,
+                     double y_wall, int32_t wall_dir, double* theta_deg, double* xc, double* yc,
+                     double* radius, int64_t* n_points) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return contact_angle(h->g, 0, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, xc, yc,
+                         radius, n_points);
+}
+
+int lb_fill_length(lb_handle* h, int32_t x_lo, int32_t x_hi, double width, double* length) {
+    if (!h || !length) return fail(LB_EINVAL, "NULL argument");
+    if (!(width > 0)) return fail(LB_EINVAL, "width must be positive");
+    if (x_hi < x_lo) return fail(LB_EINVAL, "x_hi < x_lo");
+    double s[6];
+    int rc = reduce_member(h->g, 0, x_lo, x_hi, s);
+    if (rc) return rc;
+    *length = s[5] / width;
+    return LB_OK;
+}
+
+int lb_set_wall_dphi(lb_handle* h, const double* wall_dphi) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    Member& mb = h->g.m[0];
+    const int64_t n = (int64_t)mb.p.nx * mb.p.ny;
+    if (wall_dphi)
+        for (int64_t i = 0; i < n; ++i)
+            if (mb.solid[i] && !is_finite(wall_dphi[i])) return fail(LB_EINVAL, "non-finite wall_dphi");
+    HIPCHK(hipStreamSynchronize(h->g.stream));
+    return upload_dphi(mb, wall_dphi, h->g.stream);
+}
+
+int lb_save(lb_handle* h, const char* path) {
+    if (!h || !path) return fail(LB_EINVAL, "NULL argument");
+    Group& g = h->g;
+    Member& mb = g.m[0];
+    HIPCHK(hipStreamSynchronize(g.stream));
+    std::vector<char> buf(mb.L.buf_bytes);
+    HIPCHK(hipMemcpy(buf.data(), mb.view.buf[g.parity], buf.size(), hipMemcpyDeviceToHost));
+    CkptHeader hd{};
+    std::memcpy(hd.magic, "LBMCKPT1", 8);
+    hd.version = 1;
+    hd.parity = 0;
+    hd.step = g.step;
+    hd.params = mb.p;
+    hd.buf_bytes = buf.size();
+    hd.n = (uint64_t)mb.p.nx * mb.p.ny;
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(LB_EIO, std::string("cannot open ") + path);
+    bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1 &&
+              std::fwrite(mb.solid.data(), 1, hd.n, fp) == hd.n &&
+              std::fwrite(mb.dphi.data(), 8, hd.n, fp) == hd.n &&
+              std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(LB_EIO, std::string("write failed: ") + path);
+    return LB_OK;
+}
+
+int lb_load(lb_handle* h, const char* path) {
+    if (!h || !path) return fail(LB_EINVAL, "NULL argument");
+    Group& g = h->g;
+    Member& mb = g.m[0];
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(LB_EIO, std::string("cannot open ") + path);
+    CkptHeader hd{};
+    std::vector<uint8_t> solid;
+    std::vector<double> dphi;
+    std::vector<char> buf;
+    bool ok = std::fread(&hd, sizeof(hd), 1, fp) == 1 && std::memcmp(hd.magic, "LBMCKPT1", 8) == 0 &&
+              hd.version == 1 && hd.n == (uint64_t)mb.p.nx * mb.p.ny && hd.buf_bytes == mb.L.buf_bytes;
+    if (ok) {
+        solid.resize(hd.n);
+        dphi.resize(hd.n);
+        buf.resize(hd.buf_bytes);
+        ok = std::fread(solid.data(), 1, hd.n, fp) == hd.n &&
+             std::fread(dphi.data(), 8, hd.n, fp) == hd.n &&
+             std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
+    }
+    std::fclose(fp);
+    if (!ok) return fail(LB_EIO, std::string("not a matching checkpoint: ") + path);
+    lb_params a = hd.params, b = mb.p;
+    a.diag_every = b.diag_every = 0;
+    if (std::memcmp(&a, &b, sizeof(lb_params)) != 0 || solid != mb.solid)
+        return fail(LB_EINVAL, "checkpoint parameters or mask differ from the handle");
+    HIPCHK(hipStreamSynchronize(g.stream));
+    HIPCHK(hipMemcpy(mb.view.buf[0], buf.data(), buf.size(), hipMemcpyHostToDevice));
+    g.parity = 0;
+    g.step = hd.step;
+    return upload_dphi(mb, dphi.data(), g.stream);
+}
+
+int lb_set_tuning(lb_handle* h, const lb_tuning* t) {
+    if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(h->g.stream));
+    return set_tuning(h->g, t->block_x, t->rows_per_block);
+}
+
+int lb_get_tuning(lb_handle* h, lb_tuning* t) {
+    if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+    *t = lb_tuning{h->g.block_x, h->g.rows};
+    return LB_OK;
+}
+
+int lb_autotune(lb_handle* h, int32_t steps_per_trial, lb_tuning* chosen) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return autotune(h->g, steps_per_trial, chosen);
+}
+
+int lb_free(lb_handle* h) {
+    if (!h) return LB_OK;
+    free_group(h->g);
+    delete h;
+    return LB_OK;
+}
+
+int lb_dphi_for_angle(double theta_deg, double kappa, double A, double B, double* dphi) {
+    if (!dphi) return fail(LB_EINVAL, "dphi is NULL");
+    if (!(theta_deg >= 0.0 && theta_deg <= 180.0)) return fail(LB_EINVAL, "theta must be in [0, 180]");
+    if (!(kappa > 0) || !(B > 0) || !(A < 0)) return fail(LB_EINVAL, "need kappa > 0, B > 0, A < 0");
+    // The closed form assumes the symmetric double well B = -A = a.
+    if (std::fabs(A + B) > 1e-12 * B) return fail(LB_EINVAL, "closed form needs B == -A");
+    const double a = B;
+    const double th = theta_deg * M_PI / 180.0;
+    const double s = std::sin(th);
+    const double alpha = std::acos(s * s);
+    const double c3 = std::cos(alpha / 3.0);
+    const double sg = th > M_PI / 2 ? 1.0 : (th < M_PI / 2 ? -1.0 : 0.0);
+    *dphi = 2.0 * sg * std::sqrt(std::max(0.0, c3 * (1.0 - c3))) / std::sqrt(2.0 * kappa / a);
+    return LB_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
+                  const double* const* wall_dphi, const double* const* phi0,
+                  const double* const* rho0, const double* const* ux0, const double* const* uy0,
+                  void* stream, const lb_tuning* tuning, lb_batch** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !params || !solid || !phi0) return fail(LB_EINVAL, "need n >= 1, params, solid, phi0");
+    std::vector<int64_t> nf(n);
+    for (int k = 0; k < n; ++k) {
+        int rc = validate_params(&params[k]);
+        if (!rc)
+            rc = validate_inputs(&params[k], solid[k], wall_dphi ? wall_dphi[k] : nullptr, phi0[k],
+                                 rho0 ? rho0[k] : nullptr, ux0 ? ux0[k] : nullptr,
+                                 uy0 ? uy0[k] : nullptr, &nf[k]);
+        if (rc) return fail(rc, "member " + std::to_string(k) + ": " + g_err);
+        if (params[k].storage != params[0].storage || params[k].collision != params[0].collision ||
+            params[k].zero_u_feq != params[0].zero_u_feq ||
+            params[k].zero_u_geq != params[0].zero_u_geq || params[k].diag_every != params[0].diag_every)
+            return fail(LB_EINVAL, "members must share storage, collision, Step 2 flags and diag_every");
+    }
+    int bx = 256, rows = 32;
+    if (tuning) {
+        int rc = check_tuning(tuning->block_x, tuning->rows_per_block);
+        if (rc) return rc;
+        bx = tuning->block_x;
+        rows = tuning->rows_per_block;
+    }
+    lb_batch* b = new lb_batch();
+    Group& g = b->g;
+    g.batched = true;
+    g.stream = reinterpret_cast<hipStream_t>(stream);
+    g.block_x = bx;
+    g.rows = rows;
+    g.m.resize(n);
+    size_t total = 0;
+    size_t tiles_max = 0;
+    std::vector<size_t> offs(n);
+    for (int k = 0; k < n; ++k) {
+        g.m[k].L = make_layout(params[k].nx, params[k].ny, params[k].storage);
+        offs[k] = total;
+        total += round_up(g.m[k].L.total, 256);
+        tiles_max += g.m[k].L.n_tiles_max;
+    }
+    g.n_tiles = (int)tiles_max;
+    const size_t off_tiles = total;
+    const size_t off_first = off_tiles + round_up(tiles_max * sizeof(Tile), 256);
+    const size_t off_part = off_first + round_up((size_t)(n + 1) * 4, 256);
+    const size_t off_diag = off_part + round_up(tiles_max * kPartials * 8, 256);
+    const size_t off_flag = off_diag + round_up((size_t)n * kPartials * 8, 256);
+    const size_t off_views = off_flag + round_up((size_t)n * 4, 256);
+    const size_t bytes = off_views + round_up((size_t)n * sizeof(View), 256);
+    hipError_t e = hipMalloc(&g.batch_alloc, bytes);
+    if (e != hipSuccess) {
+        g.batch_alloc = nullptr;
+        delete b;
+        return fail(LB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    char* base = g.batch_alloc;
+    g.d_tiles = reinterpret_cast<Tile*>(base + off_tiles);
+    g.d_first = reinterpret_cast<int32_t*>(base + off_first);
+    g.d_partials = reinterpret_cast<double*>(base + off_part);
+    g.d_diag = reinterpret_cast<double*>(base + off_diag);
+    g.d_flag = reinterpret_cast<int32_t*>(base + off_flag);
+    g.d_views = reinterpret_cast<View*>(base + off_views);
+    int rc = LB_OK;
+    if (launch_fill(base + off_tiles, 0, bytes - off_tiles, g.stream) != hipSuccess)
+        rc = fail(LB_EHIP, "fill failed");
+    std::vector<View> views(n);
+    for (int k = 0; k < n && !rc; ++k) {
+        g.m[k].base = base + offs[k];
+        rc = init_member(g.m[k], &params[k], solid[k], wall_dphi ? wall_dphi[k] : nullptr, phi0[k],
+                         rho0 ? rho0[k] : nullptr, ux0 ? ux0[k] : nullptr, uy0 ? uy0[k] : nullptr,
+                         g.stream);
+        g.m[k].n_fluid = nf[k];
+        views[k] = g.m[k].view;
+    }
+    if (!rc && hipMemcpy(g.d_views, views.data(), n * sizeof(View), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(LB_EHIP, "copy of member views failed");
+    if (!rc) rc = build_tiles(g);
+    if (rc) {
+        const std::string msg = g_err;
+        free_group(g);
+        delete b;
+        return fail(rc, msg);
+    }
+    *out = b;
+    return LB_OK;
+}
+
+int lb_batch_step(lb_batch* b, int64_t nsteps) {
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    return group_step(b->g, nsteps);
+}
+
+static int check_member(lb_batch* b, int32_t k) {
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    if (k < 0 || k >= (int32_t)b->g.m.size()) return fail(LB_EINVAL, "member index out of range");
+    return LB_OK;
+}
+
+int lb_batch_read_fields(lb_batch* b, int32_t k, double* phi, double* rho, double* ux, double* uy) {
+    int rc = check_member(b, k);
+    if (rc) return rc;
+    rc = read_fields(b->g, k, phi, rho, ux, uy);
+    if (rc) return rc;
+    return check_flag(b->g);
+}
+
+int lb_batch_read_populations(lb_batch* b, int32_t k, double* f, double* g) {
+    int rc = check_member(b, k);
+    if (rc) return rc;
+    return read_populations(b->g, k, f, g);
+}
+
+int lb_batch_contact_angle(lb_batch* b, int32_t k, double x_lo, double x_hi, double y_lo,
+                           double y_hi, double y_wall, int32_t wall_dir, double* theta_deg) {
+    int rc = check_member(b, k);
+    if (rc) return rc;
+    return contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
+                         nullptr, nullptr, nullptr);
+}
+
+int lb_batch_get_tuning(lb_batch* b, lb_tuning* t) {
+    if (!b || !t) return fail(LB_EINVAL, "NULL argument");
+    *t = lb_tuning{b->g.block_x, b->g.rows};
+    return LB_OK;
+}
+
+int lb_batch_free(lb_batch* b) {
+    if (!b) return LB_OK;
+    free_group(b->g);
+    delete b;
+    return LB_OK;
+}
+
+}  // extern "C"

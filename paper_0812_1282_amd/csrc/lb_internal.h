@@ -1,0 +1,94 @@
+// Internal declarations shared by the kernels (lb_kernels.hip) and the host
+// side of the C ABI (lb_api.hip). Nothing here is visible to callers of lb.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Device-memory layout of one lattice ("arena", one allocation):
+//   buf[0], buf[1]  population buffers (A/B ping-pong). Each holds the 18
+//                   planes f_0..f_8, g_0..g_8 of pitch*ny elements (row pitch
+//                   rounded up to 64 elements). In the 16-bit formats the
+//                   planes f_0..f_8, g_1..g_8 are 16-bit and g_0 is an FP32
+//                   plane placed after them.
+//   nbr             pitch*ny bytes. 0xFF marks a solid node; for a fluid node
+//                   bit (i-1) is set when the pull source r - e_i is solid.
+//   grec            pitch*ny bytes, used at solid nodes: bits 0..3 mark fluid
+//                   axis neighbours s + e_1..e_4, bits 4..7 fluid diagonal
+//                   neighbours s + e_5..e_8.
+//   dphi            pitch*ny wall gradients d_perp phi (FP64 for the FP64
+//                   format, FP32 otherwise), read at solid nodes.
+//   misc            per-workgroup FP64 partial sums, the last diagnostics,
+//                   the sticky numeric-error flag, the crossing counter and
+//                   this lattice's View and tile table.
+// buf[1] also serves as staging space for initial fields, read-back fields and
+// contact-line crossings between steps (it is rewritten in full by every step).
+// ---------------------------------------------------------------------------
+
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+enum Collision { CO_BGK = 0, CO_MRT = 1 };
+
+constexpr int kPitchAlign = 64;     // elements
+constexpr int kNR = 8;              // rows of the phi ring buffer in LDS
+constexpr int kPartials = 8;        // doubles per workgroup partial record
+
+struct View {
+    int32_t nx, ny, pitch, tiles_x;
+    int64_t plane;            // elements per population plane
+    int64_t g0_offset;        // byte offset of the FP32 g_0 plane (16-bit formats)
+    char* buf[2];
+    const uint8_t* nbr;
+    const uint8_t* grec;
+    const void* dphi;
+    double A, B, kappa, Gamma, tau_alpha, tau_beta, inv_tau_phi;
+    float ref[9];             // rest-state shift of f (16-bit formats)
+    int32_t zero_u_feq, zero_u_geq;
+    int32_t storage, collision;
+};
+
+struct Tile {
+    int32_t member, tx, ty, first;  // first: index of this member's first tile
+};
+
+// Offsets of one lattice inside its arena.
+struct Layout {
+    int32_t pitch;
+    int64_t plane;
+    size_t buf_bytes;       // bytes of one population buffer
+    size_t g0_offset;
+    size_t off_buf0, off_buf1, off_nbr, off_grec, off_dphi, off_misc;
+    size_t n_partials;      // partial records available
+    size_t off_partials, off_diag, off_flag, off_counter, off_view, off_tiles;
+    size_t n_tiles_max;
+    size_t total;
+};
+
+Layout make_layout(int nx, int ny, int storage);
+
+// Kernel launchers (lb_kernels.hip). All enqueue on `stream` and return the
+// hipError_t of the launch.
+hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, const View* d_views,
+                        const Tile* d_tiles, int n_blocks_1d, int grid_x, int grid_y, int rows,
+                        int parity, double* partials, hipStream_t stream);
+hipError_t launch_finalize(const Tile* d_tiles, const int32_t* member_first, int n_members,
+                           int n_records_single, const double* partials, double* diag_out,
+                           int32_t* flag, hipStream_t stream);
+hipError_t launch_init_state(const View& v, const double* phi0, const double* rho0,
+                             const double* ux0, const double* uy0, hipStream_t stream);
+hipError_t launch_moments(const View& v, int parity, double* fields, double* partials,
+                          int n_records, int32_t x_lo, int32_t x_hi, hipStream_t stream);
+hipError_t launch_read_plane(const View& v, int parity, int plane, double* out,
+                             hipStream_t stream);
+hipError_t launch_crossings(const View& v, int parity, void* points, int64_t capacity,
+                            unsigned long long* counter, hipStream_t stream);
+hipError_t launch_fill(void* dst, uint8_t value, size_t bytes, hipStream_t stream);
+
+struct Crossing {
+    uint64_t key;   // (node << 2) | (axis << 1) | (phi > 0 at the base node)
+    double t;       // fraction along the link from the base node
+};
+
+}  // namespace lbm

@@ -1,0 +1,836 @@
+// HIP kernels for gfx950 of the binary free-energy lattice Boltzmann method of
+// Pooley, Kusumaatmaja and Yeomans (arXiv:0812.1282).
+//
+// The hot path is sweep_kernel: one fused pass per timestep (pull-stream with
+// mid-link bounce-back, moments, LDS phi tile with wetting ghosts, stencils,
+// mu and p0, tau(phi), equilibria, BGK or MRT collision, store). It is bound by
+// HBM bandwidth: every population is read once and written once per step.
+//
+// Work decomposition: a workgroup of BX threads owns BX consecutive columns
+// (one per thread, coalesced along x) and walks `rows` consecutive rows of a
+// strip. phi of the rows it needs is kept in an 8-row ring in LDS, two rows
+// ahead of the row being collided, with two halo columns on each side; the
+// pulled g of the two look-ahead rows stays in registers, so every g value is
+// loaded once for phi and reused by the collision.
+#include "lb_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace lbm {
+
+// D2Q9 vectors of Sec. III.A and their opposites.
+__device__ constexpr int EX[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
+__device__ constexpr int EY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
+__device__ constexpr int OPP[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+
+// ------------------------------------------------------------------ storage
+
+__device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline uint16_t float_to_bf16(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int S>
+struct Pop;
+
+template <>
+struct Pop<ST_F64> {
+    using real = double;
+    static constexpr bool kShifted = false;
+    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
+        return reinterpret_cast<const double*>(b)[p * v.plane + i];
+    }
+    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
+        __builtin_nontemporal_store(x, reinterpret_cast<double*>(b) + p * v.plane + i);
+    }
+};
+
+template <>
+struct Pop<ST_F32> {
+    using real = float;
+    static constexpr bool kShifted = false;
+    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
+        return reinterpret_cast<const float*>(b)[p * v.plane + i];
+    }
+    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
+        __builtin_nontemporal_store(x, reinterpret_cast<float*>(b) + p * v.plane + i);
+    }
+};
+
+// 16-bit formats: f_i stored as f_i - ref_i, g_1..g_8 stored as is, g_0 in FP32.
+template <int S>
+struct Pop16 {
+    using real = float;
+    static constexpr bool kShifted = true;
+    __device__ static float dec(uint16_t h) {
+        if constexpr (S == ST_F16S) {
+            _Float16 x = __builtin_bit_cast(_Float16, h);
+            return (float)x;
+        } else {
+            return bf16_to_float(h);
+        }
+    }
+    __device__ static uint16_t enc(float x) {
+        if constexpr (S == ST_F16S) {
+            _Float16 h = (_Float16)x;
+            return __builtin_bit_cast(uint16_t, h);
+        } else {
+            return float_to_bf16(x);
+        }
+    }
+    // f planes return the stored deviation; pull() adds the shift.
+    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
+        const uint16_t* h = reinterpret_cast<const uint16_t*>(b);
+        if (p < 9) return dec(h[p * v.plane + i]);
+        if (p == 9) return reinterpret_cast<const float*>(b + v.g0_offset)[i];
+        return dec(h[(p - 1) * v.plane + i]);
+    }
+    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
+        uint16_t* h = reinterpret_cast<uint16_t*>(b);
+        if (p < 9) {
+            __builtin_nontemporal_store(enc(x - v.ref[p]), h + p * v.plane + i);
+        } else if (p == 9) {
+            __builtin_nontemporal_store(x, reinterpret_cast<float*>(b + v.g0_offset) + i);
+        } else {
+            __builtin_nontemporal_store(enc(x), h + (p - 1) * v.plane + i);
+        }
+    }
+};
+template <>
+struct Pop<ST_F16S> : Pop16<ST_F16S> {};
+template <>
+struct Pop<ST_BF16S> : Pop16<ST_BF16S> {};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Pull the nine populations of set `base` (0 = f, 9 = g) that arrive at fluid
+// node (x, y): from r - e_i, or, if that node is solid, the node's own
+// post-collision value in the opposite direction (mid-link bounce-back).
+template <int S>
+__device__ inline void pull(const char* src, const View& v, int base, int x, int xm, int xp,
+                            int64_t r0, int64_t rm, int64_t rp, uint32_t nb,
+                            typename Pop<S>::real out[9]) {
+    const int64_t self = r0 + x;
+    const int64_t from[9] = {self,   r0 + xm, r0 + xp, rm + x, rp + x,
+                             rm + xm, rp + xp, rm + xp, rp + xm};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool bb = (i > 0) && ((nb >> (i - 1)) & 1u);
+        out[i] = Pop<S>::ld(src, v, base + (bb ? OPP[i] : i), bb ? self : from[i]);
+        if constexpr (Pop<S>::kShifted) {
+            if (base == 0) out[i] += bb ? v.ref[OPP[i]] : v.ref[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ the sweep
+
+template <int S, int COLL, int BX, bool DIAG>
+__global__ __launch_bounds__(BX) void sweep_kernel(const View* __restrict__ views,
+                                                   const Tile* __restrict__ tiles, int rows,
+                                                   int parity, double* __restrict__ partials) {
+    using P = Pop<S>;
+    using real = typename P::real;
+    constexpr int W = BX + 4;
+    __shared__ real sphi[kNR][W];
+
+    int member = 0, tx, ty;
+    if (tiles) {
+        const Tile tl = tiles[blockIdx.x];
+        member = tl.member;
+        tx = tl.tx;
+        ty = tl.ty;
+    } else {
+        tx = blockIdx.x;
+        ty = blockIdx.y;
+    }
+    const View v = views[member];  // kept in SGPRs for the whole strip
+    const int nx = v.nx, ny = v.ny, pitch = v.pitch;
+    // Select with ?: rather than indexing buf[] by a runtime value, which
+    // would force the View copy into private (scratch) memory.
+    const char* __restrict__ src = parity ? v.buf[1] : v.buf[0];
+    char* __restrict__ dst = parity ? v.buf[0] : v.buf[1];
+    const uint8_t* __restrict__ nbr = v.nbr;
+
+    const int t = threadIdx.x;
+    const int x0 = tx * BX;
+    const int y0 = ty * rows;
+    const int y1 = min(y0 + rows, ny);
+    const int xc = x0 + t;
+    const bool active = xc < nx;
+    const int x = xc % nx;
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    // Threads 0..3 also compute phi of the halo columns x0-2, x0-1, x0+BX, x0+BX+1.
+    const bool halo = t < 4;
+    const int hcol = t < 2 ? t : BX + t;
+    const int hx = ((x0 - 2 + hcol) % nx + nx) % nx;
+    const int hxm = hx == 0 ? nx - 1 : hx - 1;
+    const int hxp = hx == nx - 1 ? 0 : hx + 1;
+
+    const real rA = (real)v.A, rB = (real)v.B, rK = (real)v.kappa, rG = (real)v.Gamma;
+    const real ta = (real)v.tau_alpha, tb = (real)v.tau_beta, itp = (real)v.inv_tau_phi;
+    const real* __restrict__ dphi = reinterpret_cast<const real*>(v.dphi);
+
+    // phi of row yy into the ring; returns the pulled g of this thread's column.
+    auto phi_row = [&](int yy, real g[9], uint32_t& nb_out) {
+        const int y = wrap(yy, ny);
+        const int64_t r0 = (int64_t)y * pitch;
+        const int64_t rm = (int64_t)wrap(y - 1, ny) * pitch;
+        const int64_t rp = (int64_t)wrap(y + 1, ny) * pitch;
+        const uint32_t nb = nbr[r0 + x];
+        nb_out = nb;
+        real ph = 0;
+        if (nb != 0xFFu) {
+            pull<S>(src, v, 9, x, xm, xp, r0, rm, rp, nb, g);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) ph += g[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = 0;
+        }
+        sphi[yy & (kNR - 1)][t + 2] = ph;
+        if (halo) {
+            const uint32_t hnb = nbr[r0 + hx];
+            real hp = 0;
+            if (hnb != 0xFFu) {
+                real hg[9];
+                pull<S>(src, v, 9, hx, hxm, hxp, r0, rm, rp, hnb, hg);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) hp += hg[i];
+            }
+            sphi[yy & (kNR - 1)][hcol] = hp;
+        }
+    };
+
+    real gA[9], gB[9], gN[9];
+    uint32_t nbA, nbB, nbN;
+    {
+        real gtmp[9];
+        uint32_t nbt;
+        phi_row(y0 - 2, gtmp, nbt);
+        phi_row(y0 - 1, gtmp, nbt);
+    }
+    phi_row(y0, gA, nbA);
+    phi_row(y0 + 1, gB, nbB);
+
+    double d_rho = 0.0, d_phi = 0.0, d_ke = 0.0, d_umax = 0.0, d_n = 0.0;
+
+    for (int y = y0; y < y1; ++y) {
+        phi_row(y + 2, gN, nbN);
+        __syncthreads();
+
+        if (active && nbA != 0xFFu) {
+            const uint32_t nb = nbA;
+            const int ym = wrap(y - 1, ny), yp = wrap(y + 1, ny);
+            const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch,
+                          rp = (int64_t)yp * pitch;
+            real f[9];
+            pull<S>(src, v, 0, x, xm, xp, r0, rm, rp, nb, f);
+
+            const int c = t + 2;
+            const real ph = sphi[y & (kNR - 1)][c];
+            // phi at the eight neighbours k = 1..8 (ghost values at solid ones).
+            real pn[9];
+#pragma unroll
+            for (int k = 1; k < 9; ++k) pn[k] = sphi[(y + EY[k]) & (kNR - 1)][c + EX[k]];
+            if (nb != 0u) {
+#pragma unroll
+                for (int k = 1; k < 9; ++k) {
+                    if ((nb >> (OPP[k] - 1)) & 1u) {
+                        // Solid neighbour s = r + e_k: mean of phi over its fluid
+                        // axis neighbours (else diagonal ones) minus the wall
+                        // gradient (times sqrt 2 across a diagonal).
+                        const int sy = wrap(y + EY[k], ny);
+                        const int sxw = EX[k] == 0 ? x : (EX[k] > 0 ? xp : xm);
+                        const int64_t s = (int64_t)sy * pitch + sxw;
+                        const uint32_t rec = v.grec[s];
+                        const real dw = dphi[s];
+                        real sum = 0;
+                        int cnt = 0;
+                        const uint32_t axis = rec & 0xFu;
+                        const int m0 = axis ? 1 : 5;
+                        const uint32_t bits = axis ? axis : (rec >> 4);
+#pragma unroll
+                        for (int mm = 0; mm < 4; ++mm) {
+                            if ((bits >> mm) & 1u) {
+                                const int m = m0 + mm;
+                                sum += sphi[(y + EY[k] + EY[m]) & (kNR - 1)][c + EX[k] + EX[m]];
+                                ++cnt;
+                            }
+                        }
+                        real gv = 0;
+                        if (cnt > 0)
+                            gv = sum / (real)cnt - (axis ? dw : (real)1.4142135623730951 * dw);
+                        pn[k] = gv;
+                    }
+                }
+            }
+            // Eq. (best): E = 1, W = 2, N = 3, S = 4, NE = 5, SW = 6, NW = 7, SE = 8.
+            const real gx = ((real)4 * (pn[1] - pn[2]) + (pn[5] - pn[7]) + (pn[8] - pn[6])) *
+                            (real)(1.0 / 12.0);
+            const real gy = ((real)4 * (pn[3] - pn[4]) + (pn[5] - pn[8]) + (pn[7] - pn[6])) *
+                            (real)(1.0 / 12.0);
+            const real lap = ((real)4 * (pn[1] + pn[2] + pn[3] + pn[4]) +
+                              (pn[5] + pn[6] + pn[7] + pn[8]) - (real)20 * ph) *
+                             (real)(1.0 / 6.0);
+
+            // Moments, Eq. (moments).
+            real rho = 0, jx = 0, jy = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                rho += f[i];
+                jx += (real)EX[i] * f[i];
+                jy += (real)EY[i] * f[i];
+            }
+            const real ux = jx / rho, uy = jy / rho;
+
+            if constexpr (DIAG) {
+                const double u2 = (double)ux * ux + (double)uy * uy;
+                d_rho += rho;
+                d_phi += ph;
+                d_ke += 0.5 * (double)rho * u2;
+                const double um = sqrt(u2);
+                d_umax = (um > d_umax || um != um) ? um : d_umax;
+                d_n += 1.0;
+            }
+
+            // Eqs. (chempot), (p0), (tau).
+            const real mu = ph * (rA + rB * ph * ph) - rK * lap;
+            const real p0 = rho * (real)(1.0 / 3.0) + ph * ph * (rA * (real)0.5 + rB * (real)0.75 * ph * ph);
+            const real pc = ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph);
+            const real tau = tb + (real)0.5 * (pc + (real)1) * (ta - tb);
+            const real omega = (real)1 / tau;
+
+            // Step 2: u = 0 at boundary nodes in the equilibria (flags).
+            const bool bnd = nb != 0u;
+            const bool zf = bnd && v.zero_u_feq;
+            const bool zg = bnd && v.zero_u_geq;
+            const real ufx = zf ? (real)0 : ux, ufy = zf ? (real)0 : uy;
+            const real ugx = zg ? (real)0 : ux, ugy = zg ? (real)0 : uy;
+
+            // Appendix A, Eq. (equilibrium) for i = 1..8 and Eq. (feq0).
+            const real basef = p0 - rK * ph * lap;
+            const real gxx = rK * gx * gx, gyy = rK * gy * gy, gxy = rK * gx * gy;
+            const real usf = ufx * ufx + ufy * ufy;
+            const real usg = ugx * ugx + ugy * ugy;
+            const real baseg = rG * mu;
+            real feq[9], geq[9];
+            real sf = 0, sg = 0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const real w = i < 5 ? (real)(1.0 / 3.0) : (real)(1.0 / 12.0);
+                real wxx, wyy, wxy;
+                if (i < 3) {
+                    wxx = (real)(1.0 / 3.0); wyy = (real)(-1.0 / 6.0); wxy = 0;
+                } else if (i < 5) {
+                    wxx = (real)(-1.0 / 6.0); wyy = (real)(1.0 / 3.0); wxy = 0;
+                } else {
+                    wxx = (real)(-1.0 / 24.0); wyy = (real)(-1.0 / 24.0);
+                    wxy = i < 7 ? (real)0.25 : (real)-0.25;
+                }
+                const real euf = (real)EX[i] * ufx + (real)EY[i] * ufy;
+                const real eug = (real)EX[i] * ugx + (real)EY[i] * ugy;
+                feq[i] = w * (basef + rho * euf + (real)1.5 * rho * (euf * euf - usf * (real)(1.0 / 3.0))) +
+                         (wxx * gxx + wyy * gyy + wxy * gxy);
+                geq[i] = w * (baseg + ph * eug + (real)1.5 * ph * (eug * eug - usg * (real)(1.0 / 3.0)));
+                sf += feq[i];
+                sg += geq[i];
+            }
+            feq[0] = rho - sf;
+            geq[0] = ph - sg;
+
+            // Collision.
+            real fo[9];
+            if constexpr (COLL == CO_BGK) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fo[i] = f[i] - omega * (f[i] - feq[i]);
+            } else {
+                // Eq. (mrtlb) with S = diag(0,1,1,0,1,0,1,w,w) written in moment space:
+                // f' = f^eq + (projection of f - f^eq on the conserved modes 0, 3, 5)
+                //      + (1 - w)(projection on the stress modes 7, 8),
+                // using the orthogonality of the rows of M (norms 9,36,36,6,12,6,12,4,4).
+                real d[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) d[i] = f[i] - feq[i];
+                const real m7 = (d[1] + d[2] - d[3] - d[4]) * (real)0.25 * ((real)1 - omega);
+                const real m8 = (d[5] + d[6] - d[7] - d[8]) * (real)0.25 * ((real)1 - omega);
+                // j - j^eq is zero unless Step 2 removed u from f^eq.
+                const real qx = zf ? jx * (real)(1.0 / 6.0) : (real)0;
+                const real qy = zf ? jy * (real)(1.0 / 6.0) : (real)0;
+                fo[0] = feq[0];
+                fo[1] = feq[1] + m7 + qx;
+                fo[2] = feq[2] + m7 - qx;
+                fo[3] = feq[3] - m7 + qy;
+                fo[4] = feq[4] - m7 - qy;
+                fo[5] = feq[5] + m8 + qx + qy;
+                fo[6] = feq[6] + m8 - qx - qy;
+                fo[7] = feq[7] - m8 - qx + qy;
+                fo[8] = feq[8] - m8 + qx - qy;
+            }
+            const int64_t self = r0 + x;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) P::st(dst, v, i, self, fo[i]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) P::st(dst, v, 9 + i, self, gA[i] - itp * (gA[i] - geq[i]));
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            gA[i] = gB[i];
+            gB[i] = gN[i];
+        }
+        nbA = nbB;
+        nbB = nbN;
+    }
+
+    if constexpr (DIAG) {
+        // Wavefront reduction, then across the BX/64 wavefronts in a fixed order.
+        __shared__ double red[BX / 64][5];
+        double vals[5] = {d_rho, d_phi, d_ke, d_umax, d_n};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            double a = vals[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double b = __shfl_xor(a, off, 64);
+                if (k == 3)
+                    a = (b > a || b != b) ? b : a;
+                else
+                    a += b;
+            }
+            vals[k] = a;
+        }
+        const int lane = t & 63, wv = t >> 6;
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) red[wv][k] = vals[k];
+        }
+        __syncthreads();
+        if (t == 0) {
+            double o[5] = {0, 0, 0, 0, 0};
+            for (int w = 0; w < BX / 64; ++w) {
+                o[0] += red[w][0];
+                o[1] += red[w][1];
+                o[2] += red[w][2];
+                o[3] = (red[w][3] > o[3] || red[w][3] != red[w][3]) ? red[w][3] : o[3];
+                o[4] += red[w][4];
+            }
+            const int64_t rec = tiles ? (int64_t)blockIdx.x
+                                      : (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+            double* out = partials + rec * kPartials;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) out[k] = o[k];
+            out[5] = 0.0;
+        }
+    }
+}
+
+// Sum per-workgroup partial records in a fixed order: one workgroup per member.
+__global__ __launch_bounds__(256) void finalize_kernel(const int32_t* __restrict__ member_first,
+                                                       int n_records_single,
+                                                       const double* __restrict__ partials,
+                                                       double* __restrict__ diag_out,
+                                                       int32_t* __restrict__ flag) {
+    const int m = blockIdx.x;
+    const int first = member_first ? member_first[m] : 0;
+    const int last = member_first ? member_first[m + 1] : n_records_single;
+    __shared__ double red[256][6];
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = first + (int)threadIdx.x; r < last; r += 256) {
+        const double* p = partials + (int64_t)r * kPartials;
+        a[0] += p[0];
+        a[1] += p[1];
+        a[2] += p[2];
+        a[3] = (p[3] > a[3] || p[3] != p[3]) ? p[3] : a[3];
+        a[4] += p[4];
+        a[5] += p[5];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = a[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            double* x = red[threadIdx.x];
+            const double* y = red[threadIdx.x + s];
+            x[0] += y[0];
+            x[1] += y[1];
+            x[2] += y[2];
+            x[3] = (y[3] > x[3] || y[3] != y[3]) ? y[3] : x[3];
+            x[4] += y[4];
+            x[5] += y[5];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = diag_out + (int64_t)m * kPartials;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o[k] = red[0][k];
+        const bool bad = !isfinite(red[0][0]) || !isfinite(red[0][1]) || !isfinite(red[0][2]) ||
+                         !(red[0][3] == red[0][3]);
+        if (bad) flag[m] = 1;
+    }
+}
+
+// ------------------------------------------------------------------ initial state
+
+// S_0 = equilibria of the initial fields (ghost phi at solid nodes, stencils of
+// Eq. (best), Appendix A with the initial velocity), arithmetic in FP64, then
+// "un-streamed" into buf[0] so that the first pull of the sweep yields S_0:
+// the population S_0 f_i(r) is stored at the node it would have left, r - e_i,
+// or, across a solid link, at r in the opposite direction.
+template <int S>
+__global__ __launch_bounds__(256) void init_kernel(View v, const double* __restrict__ phi0,
+                                                   const double* __restrict__ rho0,
+                                                   const double* __restrict__ ux0,
+                                                   const double* __restrict__ uy0) {
+    const int64_t n = (int64_t)v.nx * v.ny;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % v.nx), y = (int)(id / v.nx);
+    const int nx = v.nx, ny = v.ny, pitch = v.pitch;
+    const int64_t r = (int64_t)y * pitch + x;
+    const uint32_t nb = v.nbr[r];
+    if (nb == 0xFFu) return;
+    auto host_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * nx + wrap(xx, nx); };
+    auto dev_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * pitch + wrap(xx, nx); };
+    const bool f64 = S == ST_F64;
+    auto phi_at = [&](int xx, int yy) -> double {
+        const int64_t s = dev_idx(xx, yy);
+        if (v.nbr[s] != 0xFFu) return phi0[host_idx(xx, yy)];
+        const uint32_t rec = v.grec[s];
+        const double dw = f64 ? reinterpret_cast<const double*>(v.dphi)[s]
+                              : (double)reinterpret_cast<const float*>(v.dphi)[s];
+        const uint32_t axis = rec & 0xFu;
+        const uint32_t bits = axis ? axis : (rec >> 4);
+        const int m0 = axis ? 1 : 5;
+        double sum = 0;
+        int cnt = 0;
+        for (int mm = 0; mm < 4; ++mm)
+            if ((bits >> mm) & 1u) {
+                sum += phi0[host_idx(xx + EX[m0 + mm], yy + EY[m0 + mm])];
+                ++cnt;
+            }
+        if (cnt == 0) return 0.0;
+        return sum / cnt - (axis ? dw : 1.4142135623730951 * dw);
+    };
+    double pn[9];
+    for (int k = 0; k < 9; ++k) pn[k] = phi_at(x + EX[k], y + EY[k]);
+    const double ph = pn[0];
+    const double gx = (4.0 * (pn[1] - pn[2]) + (pn[5] - pn[7]) + (pn[8] - pn[6])) / 12.0;
+    const double gy = (4.0 * (pn[3] - pn[4]) + (pn[5] - pn[8]) + (pn[7] - pn[6])) / 12.0;
+    const double lap = (4.0 * (pn[1] + pn[2] + pn[3] + pn[4]) + (pn[5] + pn[6] + pn[7] + pn[8]) -
+                        20.0 * ph) / 6.0;
+    const int64_t hi = (int64_t)y * nx + x;
+    const double rho = rho0[hi], ux = ux0[hi], uy = uy0[hi];
+    const double mu = ph * (v.A + v.B * ph * ph) - v.kappa * lap;
+    const double p0 = rho / 3.0 + ph * ph * (0.5 * v.A + 0.75 * v.B * ph * ph);
+    const double usq = ux * ux + uy * uy;
+    double feq[9], geq[9], sf = 0, sg = 0;
+    for (int i = 1; i < 9; ++i) {
+        const double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+        double wxx, wyy, wxy;
+        if (i < 3) {
+            wxx = 1.0 / 3.0; wyy = -1.0 / 6.0; wxy = 0;
+        } else if (i < 5) {
+            wxx = -1.0 / 6.0; wyy = 1.0 / 3.0; wxy = 0;
+        } else {
+            wxx = -1.0 / 24.0; wyy = -1.0 / 24.0; wxy = i < 7 ? 0.25 : -0.25;
+        }
+        const double eu = EX[i] * ux + EY[i] * uy;
+        feq[i] = w * (p0 - v.kappa * ph * lap + rho * eu + 1.5 * rho * (eu * eu - usq / 3.0)) +
+                 v.kappa * (wxx * gx * gx + wyy * gy * gy + wxy * gx * gy);
+        geq[i] = w * (v.Gamma * mu + ph * eu + 1.5 * ph * (eu * eu - usq / 3.0));
+        sf += feq[i];
+        sg += geq[i];
+    }
+    feq[0] = rho - sf;
+    geq[0] = ph - sg;
+    char* dst = v.buf[0];
+    for (int i = 0; i < 9; ++i) {
+        const bool bb = i > 0 && ((nb >> (i - 1)) & 1u);
+        const int64_t at = bb ? r : dev_idx(x - EX[i], y - EY[i]);
+        const int pl = bb ? OPP[i] : i;
+        Pop<S>::st(dst, v, pl, at, (typename Pop<S>::real)feq[i]);
+        Pop<S>::st(dst, v, 9 + pl, at, (typename Pop<S>::real)geq[i]);
+    }
+}
+
+// ------------------------------------------------------------------ read-back
+
+// Moments of S_n at every node: optional compact FP64 fields (phi, rho, ux, uy
+// planes of nx*ny) and FP64 partial records of sums over fluid nodes (sum rho,
+// sum phi, kinetic energy, max |u|, count, and sum (1+phi)/2 for x in [x_lo, x_hi)).
+template <int S>
+__global__ __launch_bounds__(256) void moments_kernel(View v, int parity,
+                                                      double* __restrict__ fields,
+                                                      double* __restrict__ partials,
+                                                      int32_t x_lo, int32_t x_hi) {
+    using real = typename Pop<S>::real;
+    const int64_t n = (int64_t)v.nx * v.ny;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    if (id < n) {
+        const int x = (int)(id % v.nx), y = (int)(id / v.nx);
+        const int nx = v.nx, ny = v.ny;
+        const int64_t r0 = (int64_t)y * v.pitch, rm = (int64_t)wrap(y - 1, ny) * v.pitch,
+                      rp = (int64_t)wrap(y + 1, ny) * v.pitch;
+        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const uint32_t nb = v.nbr[r0 + x];
+        double ph = 0, rho = 0, ux = 0, uy = 0;
+        if (nb != 0xFFu) {
+            real f[9], g[9];
+            pull<S>((parity ? v.buf[1] : v.buf[0]), v, 0, x, xm, xp, r0, rm, rp, nb, f);
+            pull<S>((parity ? v.buf[1] : v.buf[0]), v, 9, x, xm, xp, r0, rm, rp, nb, g);
+            double jx = 0, jy = 0;
+            for (int i = 0; i < 9; ++i) {
+                rho += (double)f[i];
+                ph += (double)g[i];
+                jx += EX[i] * (double)f[i];
+                jy += EY[i] * (double)f[i];
+            }
+            ux = jx / rho;
+            uy = jy / rho;
+            const double u2 = ux * ux + uy * uy;
+            a[0] = rho;
+            a[1] = ph;
+            a[2] = 0.5 * rho * u2;
+            a[3] = sqrt(u2);
+            a[4] = 1.0;
+            if (x >= x_lo && x < x_hi) a[5] = 0.5 * (1.0 + ph);
+        }
+        if (fields) {
+            fields[id] = ph;
+            fields[n + id] = rho;
+            fields[2 * n + id] = ux;
+            fields[3 * n + id] = uy;
+        }
+    }
+    if (partials) {
+        __shared__ double red[4][6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double b = __shfl_xor(a[k], off, 64);
+                a[k] = k == 3 ? ((b > a[k] || b != b) ? b : a[k]) : a[k] + b;
+            }
+        }
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0)
+            for (int k = 0; k < 6; ++k) red[wv][k] = a[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double* o = partials + (int64_t)blockIdx.x * kPartials;
+            for (int k = 0; k < 6; ++k) o[k] = 0;
+            for (int w = 0; w < 4; ++w) {
+                for (int k = 0; k < 6; ++k)
+                    if (k == 3)
+                        o[3] = (red[w][3] > o[3] || red[w][3] != red[w][3]) ? red[w][3] : o[3];
+                    else
+                        o[k] += red[w][k];
+            }
+        }
+    }
+}
+
+// One population plane of S_n (pulled) as compact FP64 nx*ny; zero at solid nodes.
+template <int S>
+__global__ __launch_bounds__(256) void read_plane_kernel(View v, int parity, int plane,
+                                                         double* __restrict__ out) {
+    using real = typename Pop<S>::real;
+    const int64_t n = (int64_t)v.nx * v.ny;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % v.nx), y = (int)(id / v.nx);
+    const int nx = v.nx, ny = v.ny;
+    const int64_t r0 = (int64_t)y * v.pitch, rm = (int64_t)wrap(y - 1, ny) * v.pitch,
+                  rp = (int64_t)wrap(y + 1, ny) * v.pitch;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const uint32_t nb = v.nbr[r0 + x];
+    if (nb == 0xFFu) {
+        out[id] = 0.0;
+        return;
+    }
+    real p[9];
+    pull<S>((parity ? v.buf[1] : v.buf[0]), v, plane < 9 ? 0 : 9, x, xm, xp, r0, rm, rp, nb, p);
+    out[id] = (double)p[plane % 9];
+}
+
+// phi = 0 crossings on the +x and +y links of every fluid node whose far end
+// is fluid and of opposite sign (Sec. IV); compacted with an atomic counter.
+template <int S>
+__global__ __launch_bounds__(256) void crossings_kernel(View v, int parity,
+                                                        Crossing* __restrict__ pts,
+                                                        int64_t capacity,
+                                                        unsigned long long* __restrict__ counter) {
+    using real = typename Pop<S>::real;
+    const int64_t n = (int64_t)v.nx * v.ny;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % v.nx), y = (int)(id / v.nx);
+    const int nx = v.nx, ny = v.ny;
+    auto phi_at = [&](int xx, int yy, bool& fluid) -> double {
+        const int64_t r0 = (int64_t)yy * v.pitch, rm = (int64_t)wrap(yy - 1, ny) * v.pitch,
+                      rp = (int64_t)wrap(yy + 1, ny) * v.pitch;
+        const int xm = xx == 0 ? nx - 1 : xx - 1, xp = xx == nx - 1 ? 0 : xx + 1;
+        const uint32_t nb = v.nbr[r0 + xx];
+        fluid = nb != 0xFFu;
+        if (!fluid) return 0.0;
+        real g[9];
+        pull<S>((parity ? v.buf[1] : v.buf[0]), v, 9, xx, xm, xp, r0, rm, rp, nb, g);
+        double s = 0;
+        for (int i = 0; i < 9; ++i) s += (double)g[i];
+        return s;
+    };
+    bool fa;
+    const double a = phi_at(x, y, fa);
+    if (!fa) return;
+    for (int axis = 0; axis < 2; ++axis) {
+        const int x2 = axis == 0 ? (x == nx - 1 ? 0 : x + 1) : x;
+        const int y2 = axis == 0 ? y : (y == ny - 1 ? 0 : y + 1);
+        bool fb;
+        const double b = phi_at(x2, y2, fb);
+        if (!fb) continue;
+        if ((a > 0 && b < 0) || (a < 0 && b > 0)) {
+            const unsigned long long k = atomicAdd(counter, 1ull);
+            if ((int64_t)k < capacity) {
+                Crossing c;
+                c.key = ((uint64_t)id << 2) | ((uint64_t)axis << 1) | (a > 0 ? 1u : 0u);
+                c.t = a / (a - b);
+                pts[k] = c;
+            }
+        }
+    }
+}
+
+__global__ void fill_kernel(uint8_t* __restrict__ p, uint8_t value, size_t bytes) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = i; k < bytes; k += stride) p[k] = value;
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int S, int C, int BX, bool D>
+static hipError_t sweep_one(const View* views, const Tile* tiles, int n1d, int gx, int gy,
+                            int rows, int parity, double* partials, hipStream_t st) {
+    const dim3 grid = tiles ? dim3(n1d) : dim3(gx, gy);
+    hipLaunchKernelGGL((sweep_kernel<S, C, BX, D>), grid, dim3(BX), 0, st, views, tiles, rows,
+                       parity, partials);
+    return hipGetLastError();
+}
+
+template <int S, int C, int BX>
+static hipError_t sweep_d(bool diag, const View* vw, const Tile* tl, int n1d, int gx, int gy,
+                          int rows, int par, double* parts, hipStream_t st) {
+    return diag ? sweep_one<S, C, BX, true>(vw, tl, n1d, gx, gy, rows, par, parts, st)
+                : sweep_one<S, C, BX, false>(vw, tl, n1d, gx, gy, rows, par, parts, st);
+}
+
+template <int S, int C>
+static hipError_t sweep_b(int bx, bool diag, const View* vw, const Tile* tl, int n1d, int gx,
+                          int gy, int rows, int par, double* parts, hipStream_t st) {
+    switch (bx) {
+        case 64: return sweep_d<S, C, 64>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
+        case 128: return sweep_d<S, C, 128>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
+        case 256: return sweep_d<S, C, 256>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static hipError_t sweep_c(int coll, int bx, bool diag, const View* vw, const Tile* tl, int n1d,
+                          int gx, int gy, int rows, int par, double* parts, hipStream_t st) {
+    return coll == CO_MRT ? sweep_b<S, CO_MRT>(bx, diag, vw, tl, n1d, gx, gy, rows, par, parts, st)
+                          : sweep_b<S, CO_BGK>(bx, diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
+}
+
+hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, const View* d_views,
+                        const Tile* d_tiles, int n_blocks_1d, int grid_x, int grid_y, int rows,
+                        int parity, double* partials, hipStream_t stream) {
+    switch (storage) {
+        case ST_F64:
+            return sweep_c<ST_F64>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                   grid_x, grid_y, rows, parity, partials, stream);
+        case ST_F32:
+            return sweep_c<ST_F32>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                   grid_x, grid_y, rows, parity, partials, stream);
+        case ST_F16S:
+            return sweep_c<ST_F16S>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                    grid_x, grid_y, rows, parity, partials, stream);
+        case ST_BF16S:
+            return sweep_c<ST_BF16S>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                     grid_x, grid_y, rows, parity, partials, stream);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finalize(const Tile*, const int32_t* member_first, int n_members,
+                           int n_records_single, const double* partials, double* diag_out,
+                           int32_t* flag, hipStream_t stream) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_members), dim3(256), 0, stream, member_first,
+                       n_records_single, partials, diag_out, flag);
+    return hipGetLastError();
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+#define LB_DISPATCH_STORAGE(st, KERNEL, grid, ...)                                          \
+    switch (st) {                                                                           \
+        case ST_F64: hipLaunchKernelGGL(KERNEL<ST_F64>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        case ST_F32: hipLaunchKernelGGL(KERNEL<ST_F32>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        case ST_F16S: hipLaunchKernelGGL(KERNEL<ST_F16S>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        case ST_BF16S: hipLaunchKernelGGL(KERNEL<ST_BF16S>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                               \
+    }
+
+hipError_t launch_init_state(const View& v, const double* phi0, const double* rho0,
+                             const double* ux0, const double* uy0, hipStream_t stream) {
+    const dim3 grid(blocks_for((int64_t)v.nx * v.ny));
+    LB_DISPATCH_STORAGE(v.storage, init_kernel, grid, stream, v, phi0, rho0, ux0, uy0);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const View& v, int parity, double* fields, double* partials,
+                          int n_records, int32_t x_lo, int32_t x_hi, hipStream_t stream) {
+    const dim3 grid(blocks_for((int64_t)v.nx * v.ny));
+    if (partials && (int64_t)grid.x > n_records) return hipErrorInvalidValue;
+    LB_DISPATCH_STORAGE(v.storage, moments_kernel, grid, stream, v, parity, fields, partials,
+                        x_lo, x_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_plane(const View& v, int parity, int plane, double* out,
+                             hipStream_t stream) {
+    const dim3 grid(blocks_for((int64_t)v.nx * v.ny));
+    LB_DISPATCH_STORAGE(v.storage, read_plane_kernel, grid, stream, v, parity, plane, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_crossings(const View& v, int parity, void* points, int64_t capacity,
+                            unsigned long long* counter, hipStream_t stream) {
+    const dim3 grid(blocks_for((int64_t)v.nx * v.ny));
+    Crossing* pts = reinterpret_cast<Crossing*>(points);
+    LB_DISPATCH_STORAGE(v.storage, crossings_kernel, grid, stream, v, parity, pts, capacity,
+                        counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void* dst, uint8_t value, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return hipSuccess;
+    const size_t blocks = (bytes + 255) / 256;
+    const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+    hipLaunchKernelGGL(fill_kernel, dim3(g), dim3(256), 0, stream,
+                       reinterpret_cast<uint8_t*>(dst), value, bytes);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

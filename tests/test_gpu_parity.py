@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance for the FP64 path: max |GPU - oracle| / max |oracle| <= 1e-12 per
+field and per population set after up to 1000 steps; the two sides differ only
+in rounding order (fused multiply-adds, moment-space MRT, pull vs push)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analysis
+from paper_0812_1282_amd import lbm, workloads as wl
+from tests.helpers import make_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+D60 = analysis.theory_dphi(60.0, 0.04, 0.04)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b, mask=None):
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def gpu_lattice(p, inp, storage="f64", **kw):
+    return lbm.lb_init(lbm.make_params(p, storage, **kw), inp["solid"], inp["phi0"],
+                       dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+
+
+def compare(lat, orc, solid, tol=TOL64, what=""):
+    fluid = solid == 0
+    f, g = lbm.lb_read_populations(lat)
+    of, og = orc.populations()
+    fields = lbm.lb_read_fields(lat)
+    ofields = orc.fields()
+    errs = {"f": rel(f, of, fluid), "g": rel(g, og, fluid)}
+    for name, a, b in zip(("phi", "rho", "ux", "uy"), fields, ofields):
+        if np.abs(b[fluid]).max() > 0:
+            errs[name] = rel(a, b, fluid)
+    say(f"  {what}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v)
+    assert np.all(f[:, ~fluid] == 0) and np.all(g[:, ~fluid] == 0)
+    return errs
+
+
+def run_pair(p, inp, steps, storage="f64", tol=TOL64, what="", **kw):
+    say(f"case {what}: {p['nx']}x{p['ny']} {p['collision']} {storage} steps={steps} {kw}")
+    lat = gpu_lattice(p, inp, storage, **kw)
+    orc = make_oracle(p, inp, **{k: v for k, v in kw.items() if k.startswith("zero_u")})
+    lbm.lb_step(lat, steps)
+    orc.step(steps)
+    errs = compare(lat, orc, inp["solid"], tol, what)
+    lat.close()
+    return errs
+
+
+def test_initial_state_is_equilibrium_of_inputs():
+    p = wl.params(40, 24, 1.0, 0.7, "mrt")
+    inp = wl.random_fields(p, seed=3)
+    inp["dphi"] = wl.wall_field(inp["solid"], -0.2)
+    run_pair(p, inp, 0, tol=1e-14, what="S_0")
+
+
+def test_c1_drop_bgk_1000_steps():
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    run_pair(p, inp, 1000, what="C1 100x50 BGK 60deg")
+
+
+@pytest.mark.parametrize("collision,zf,zg", [("bgk", 0, 0), ("bgk", 1, 0), ("mrt", 1, 0),
+                                             ("mrt", 0, 0), ("mrt", 1, 1)])
+def test_every_term_random_fields(collision, zf, zg):
+    """Random phi, rho and u with walls, unequal tau, tau_phi != 1 and a wall field."""
+    p = wl.params(70, 30, 1.3, 0.6, collision, Gamma=0.3, tau_phi=0.8)
+    inp = wl.random_fields(p, seed=11)
+    rng = np.random.default_rng(12)
+    inp["dphi"] = np.where(inp["solid"] != 0, rng.uniform(-0.3, 0.3, inp["solid"].shape), 0.0)
+    run_pair(p, inp, 200, what=f"random {collision} step2={zf}/{zg}", zero_u_feq=zf,
+             zero_u_geq=zg)
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("theta", [30.0, 130.0])
+def test_c2_viscosity_ratio_10(collision, theta):
+    p, inp = wl.c2_drop(collision, analysis.theory_dphi(theta, 0.04, 0.04), seed=201)
+    run_pair(p, inp, 1000, what=f"C2 256x128 {collision} {theta}deg")
+
+
+def test_capillary_geometry_plate_ends():
+    """Walls on part of the lattice only: plate ends (corner ghosts) and solid nodes
+    with fluid on one side within a wall-free periodic column."""
+    p, inp = wl.c3_capillary(256, 32, 10, D60, seed=3)
+    run_pair(p, inp, 500, what="capillary 256x32 mrt")
+
+
+def test_irregular_solid_mask():
+    """Scattered solid nodes: diagonal-only ghosts, bounce-back from all sides."""
+    p = wl.params(48, 40, 1.0, 0.6, "mrt")
+    inp = wl.random_fields(p, seed=5)
+    rng = np.random.default_rng(6)
+    solid = inp["solid"].copy()
+    solid[rng.integers(2, 38, 60), rng.integers(0, 48, 60)] = 1
+    solid[20, 10:14] = 1
+    solid[21:24, 30] = 1
+    solid[10, 5] = 1
+    solid[11, 6] = 1          # diagonal pair: each sees the other only diagonally
+    fluid = solid == 0
+    inp = {k: (np.where(fluid, v, 0.0) if isinstance(v, np.ndarray) and k != "solid" else v)
+           for k, v in inp.items()}
+    inp["solid"] = solid
+    inp["dphi"] = np.where(solid != 0, rng.uniform(-0.3, 0.3, solid.shape), 0.0)
+    run_pair(p, inp, 300, what="scattered solids")
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (67, 13), (130, 7), (64, 5)])
+def test_ragged_sizes_and_tunings(nx, ny):
+    """Sizes that are not multiples of the tile, and every tile shape, give the same
+    bits, and match the oracle."""
+    p = wl.params(nx, ny, 1.0, 0.65, "mrt")
+    inp = wl.random_fields(p, seed=nx * 100 + ny)
+    inp["dphi"] = wl.wall_field(inp["solid"], 0.1)
+    say(f"case ragged {nx}x{ny}")
+    orc = make_oracle(p, inp)
+    orc.step(60)
+    ref = None
+    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (256, 32)]:
+        lat = gpu_lattice(p, inp, "f64")
+        lbm.lb_set_tuning(lat, bx, rows)
+        lbm.lb_step(lat, 60)
+        f, g = lbm.lb_read_populations(lat)
+        if ref is None:
+            ref = (f, g)
+            compare(lat, orc, inp["solid"], what=f"ragged {nx}x{ny} tile {bx}x{rows}")
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), (bx, rows)
+        lat.close()
+
+
+def test_diagnostics_fields_and_fill_length():
+    p, inp = wl.c3_capillary(256, 32, 10, D60, seed=3)
+    say("case diagnostics capillary 256x32")
+    lat = gpu_lattice(p, inp, "f64")
+    orc = make_oracle(p, inp)
+    lbm.lb_step(lat, 300)
+    orc.step(300)
+    d = lbm.lb_diagnostics(lat)
+    od = orc.diagnostics()
+    assert d["n_fluid"] == od["n_fluid"]
+    assert d["step"] == 300
+    assert d["sum_rho"] == pytest.approx(od["sum_rho"], rel=1e-13)
+    assert d["sum_phi"] == pytest.approx(od["sum_phi"], rel=1e-12, abs=1e-10)
+    assert d["kinetic"] == pytest.approx(od["kinetic"], rel=1e-9)
+    assert d["max_u"] == pytest.approx(od["max_u"], rel=1e-9)
+    phi = orc.fields()[0]
+    l_gpu = lbm.lb_fill_length(lat, 128, 224, 30.0)
+    l_orc = (0.5 * (1 + phi[:, 128:224]))[inp["solid"][:, 128:224] == 0].sum() / 30.0
+    assert l_gpu == pytest.approx(l_orc, rel=1e-12)
+    lat.close()
+
+
+def test_conservation_on_gpu():
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(50.0, 0.04, 0.04))
+    say("case conservation C2 mrt 3000 steps")
+    lat = gpu_lattice(p, inp, "f64")
+    d0 = lbm.lb_diagnostics(lat)
+    lbm.lb_step(lat, 3000)
+    d1 = lbm.lb_diagnostics(lat)
+    assert abs(d1["sum_rho"] - d0["sum_rho"]) <= 1e-12 * d0["sum_rho"]
+    assert abs(d1["sum_phi"] - d0["sum_phi"]) <= 1e-12 * d0["n_fluid"]
+    lat.close()
+
+
+def test_contact_angle_matches_oracle_measurement():
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    say("case contact angle C1 3000 steps")
+    lat = gpu_lattice(p, inp, "f64")
+    orc = make_oracle(p, inp)
+    lbm.lb_step(lat, 3000)
+    orc.step(3000)
+    win = (0.0, 100.0, 3.5, 47.0)
+    ca = lbm.lb_contact_angle(lat, *win, 0.5, 1)
+    oca = analysis.contact_angle(orc.fields()[0], inp["solid"], 0.5, 1, *win)
+    say(f"  gpu {ca['theta']:.6f} (n={ca['n']}) oracle {oca['theta']:.6f} (n={oca['n']})")
+    assert ca["n"] == oca["n"]
+    assert ca["theta"] == pytest.approx(oca["theta"], abs=1e-8)
+    assert ca["R"] == pytest.approx(oca["R"], rel=1e-9)
+    # Eq. (theory) with equal viscosities: 60 degrees (within the lattice error).
+    assert abs(ca["theta"] - 60.0) < 3.0
+    lat.close()
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(110.0, 0.04, 0.04))
+    say("case checkpoint")
+    a = gpu_lattice(p, inp, "f64")
+    lbm.lb_step(a, 401)
+    a_f = lbm.lb_read_populations(a)
+    lbm.lb_step(a, 399)
+    ref = lbm.lb_read_populations(a)
+    b = gpu_lattice(p, inp, "f64")
+    lbm.lb_step(b, 401)
+    path = tmp_path / "state.ckpt"
+    lbm.lb_save(b, path)
+    b.close()
+    c = gpu_lattice(p, inp, "f64")
+    lbm.lb_load(c, path)
+    assert lbm.lb_get_step(c) == 401
+    mid = lbm.lb_read_populations(c)
+    assert np.array_equal(mid[0], a_f[0]) and np.array_equal(mid[1], a_f[1])
+    lbm.lb_step(c, 399)
+    out = lbm.lb_read_populations(c)
+    assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+    a.close()
+    c.close()
+
+
+def test_determinism_graph_and_memory_paths():
+    """Two runs are bitwise equal; the captured-graph path (>= 32 steps per call)
+    equals single-step calls; library-allocated and torch-allocated memory agree."""
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(70.0, 0.04, 0.04))
+    say("case determinism")
+    runs = []
+    for mem, chunk in [("torch", 96), ("torch", 96), ("torch", 1), ("library", 96)]:
+        lat = lbm.lb_init(lbm.make_params(p, "f64"), inp["solid"], inp["phi0"], dphi=inp["dphi"],
+                          rho0=inp["rho0"], device_memory=mem)
+        for _ in range(96 // chunk):
+            lbm.lb_step(lat, chunk)
+        runs.append(lbm.lb_read_populations(lat))
+        lat.close()
+    for r in runs[1:]:
+        assert np.array_equal(r[0], runs[0][0]) and np.array_equal(r[1], runs[0][1])
+
+
+def test_periodic_check_reports_nonfinite_state():
+    """diag_every > 0 enqueues the conservation sums; a run driven unstable (tau
+    close to 1/2 and a large velocity) is reported as LB_ENUMERIC."""
+    p = wl.params(64, 16, 0.5001, 0.5001, "bgk")
+    inp = wl.random_fields(p, seed=2, amp_u=0.4)
+    say("case unstable run with periodic check")
+    lat = lbm.lb_init(lbm.make_params(p, "f64", diag_every=10), inp["solid"], inp["phi0"],
+                      dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+    lbm.lb_step(lat, 2000)
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_read_fields(lat)
+    assert e.value.code == lbm.LB_ENUMERIC
+    lat.close()
+    # A stable run with the same check enabled stays clean.
+    p = wl.params(64, 16, 1.0, 1.0, "bgk")
+    inp = wl.random_fields(p, seed=2)
+    lat = lbm.lb_init(lbm.make_params(p, "f64", diag_every=10), inp["solid"], inp["phi0"])
+    lbm.lb_step(lat, 200)
+    lbm.lb_read_fields(lat)
+    assert lbm.lb_diagnostics(lat)["rc"] == 0
+    lat.close()
+
+
+def test_set_wall_dphi_matches_oracle():
+    p, inp = wl.c1_drop(seed=1, dphi_wall=0.0)
+    say("case wall gradient update")
+    lat = gpu_lattice(p, inp, "f64")
+    orc = make_oracle(p, inp)
+    lbm.lb_step(lat, 100)
+    orc.step(100)
+    new = wl.wall_field(inp["solid"], D60)
+    lbm.lb_set_wall_dphi(lat, new)
+    orc.set_wall_dphi(new)
+    lbm.lb_step(lat, 200)
+    orc.step(200)
+    compare(lat, orc, inp["solid"], what="after wall update")
+    lat.close()
