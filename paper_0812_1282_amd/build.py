@@ -16,6 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # Code object v5 loads under every ROCm 6/7 runtime, including the one
+    # bundled with the PyTorch wheel that shares this process.
+    "-mcode-object-version=5",
     # Same rounding in every template instance: contract a*b+c only within
     # one expression.
     "-ffp-contract=on",

@@ -72,6 +72,14 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_0812_1282_amd.build`")
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7). Importing it
+    # first makes the dynamic loader resolve this library's libamdhip64.so.7 to
+    # that same copy, so the process holds one HIP runtime, shared by the torch
+    # allocations and streams and by the kernels launched here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     P = ctypes.POINTER(lb_params)
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double

@@ -1,0 +1,94 @@
+"""Parity at the full 4096 x 2048 size of the large-drop workload, in the tile
+shape the benchmark times.
+
+After k steps the state at a node depends only on the initial fields within a
+bounded distance (streaming reaches 1 node per step, the phi stencil and its
+wall ghosts 2 more), so the oracle can compute sampled outputs exactly on small
+windows cut from the same initial fields: inside a margin of 3k + 4 nodes from a
+window's edges the window run equals the full-lattice run. Where a window is cut
+next to a wall, one extra solid row closes it so that the real wall row sees
+the same solid neighbours as in the full lattice."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0812_1282_amd import lbm, workloads as wl
+from tests.helpers import make_oracle
+
+pytestmark = pytest.mark.gpu
+
+K = 10
+MARGIN = 3 * K + 4
+W = 112
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _window(inp, x0, y0, nx, ny, close_top=False, close_bottom=False):
+    """Cut [x0, x0+W) x [y0, y0+W) (x periodic). close_*: replace the edge row with
+    solid so the window's periodic seam does not put fluid next to a wall."""
+    xs = (np.arange(x0, x0 + W)) % nx
+    ys = np.arange(y0, y0 + W)
+    sub = {k: (None if v is None else v[np.ix_(ys, xs)].copy()) for k, v in inp.items()}
+    if close_top:
+        sub["solid"][-1, :] = 1
+    if close_bottom:
+        sub["solid"][0, :] = 1
+    for k in ("phi0", "rho0", "ux0", "uy0"):
+        sub[k][sub["solid"] != 0] = 0.0
+    return sub
+
+
+@pytest.mark.parametrize("storage", ["f64"])
+def test_full_size_sampled_windows(storage):
+    p, inp = wl.c4_drop()
+    nx, ny = p["nx"], p["ny"]
+    say(f"case full size {nx}x{ny} {storage}, {K} steps, bench tiles")
+    lat = lbm.lb_init(lbm.make_params(p, storage), inp["solid"], inp["phi0"], dphi=inp["dphi"],
+                      rho0=inp["rho0"])
+    bx, rows = lbm.lb_get_tuning(lat)
+    say(f"  tiles {bx}x{rows}")
+    d0 = lbm.lb_diagnostics(lat)
+    lbm.lb_step(lat, K)
+    d1 = lbm.lb_diagnostics(lat)
+    assert abs(d1["sum_rho"] - d0["sum_rho"]) <= 1e-13 * d0["sum_rho"]
+    assert abs(d1["sum_phi"] - d0["sum_phi"]) <= 1e-12 * d0["n_fluid"]
+    fields = lbm.lb_read_fields(lat)
+    lat.close()
+    cases = [
+        ("contact line, bottom wall", nx // 2 + 800 - W // 2, 0, False, True),
+        ("drop apex", nx // 2 - W // 2, 800 - W // 2, False, False),
+        ("periodic seam", nx - W // 2, 1000, False, False),
+        ("top wall", 100, ny - W + 1, True, False),
+    ]
+    for name, x0, y0, top, bottom in cases:
+        if top:          # the window's first row stands for the solid row below
+            sub = _window(inp, x0, y0 - 1, nx, ny, close_bottom=True)
+            y_lo = y0 - 1
+        else:
+            sub = _window(inp, x0, y0, nx, ny, close_top=bottom)
+            y_lo = y0
+        wp = dict(p)
+        wp["nx"], wp["ny"] = W, W
+        orc = make_oracle(wp, sub)
+        orc.step(K)
+        ofields = orc.fields()
+        # rows/cols that are exact: away from cut edges (walls are real edges)
+        r0 = 0 if bottom else MARGIN
+        r1 = W if top else W - MARGIN
+        c0, c1 = MARGIN, W - MARGIN
+        xs = np.arange(x0 + c0, x0 + c1) % nx
+        ys = np.arange(y_lo + r0, y_lo + r1)
+        for fname, g, o in zip(("phi", "rho", "ux", "uy"), fields, ofields):
+            gw = g[np.ix_(ys, xs)]
+            ow = o[r0:r1, c0:c1]
+            # phi and rho relative to their scale; u absolutely (lattice units),
+            # as u is a difference of O(0.1) populations.
+            scale = max(np.abs(ow).max(), 1e-300) if fname in ("phi", "rho") else 1.0
+            err = np.abs(gw - ow).max() / scale
+            say(f"  {name}: {fname} err {err:.2e} (max |value| {np.abs(ow).max():.2e})")
+            assert err <= 1e-12, (name, fname, err)

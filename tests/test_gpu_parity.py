@@ -1,8 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerance for the FP64 path: max |GPU - oracle| / max |oracle| <= 1e-12 per
-field and per population set after up to 1000 steps; the two sides differ only
-in rounding order (fused multiply-adds, moment-space MRT, pull vs push)."""
+Tolerance for the FP64 path, after up to 1000 steps: max |GPU - oracle| /
+max |oracle| <= 1e-12 for the populations f and g (the state) and for phi and
+rho; the velocity, a difference of O(0.1) populations divided by rho ~ 1, has an
+absolute rounding floor, so it is held to max |GPU - oracle| <= 1e-12 (lattice
+units, c = 1). The two sides differ only in rounding order (fused multiply-adds,
+moment-space MRT, pull vs push streaming)."""
 import os
 import sys
 
@@ -44,9 +47,10 @@ def compare(lat, orc, solid, tol=TOL64, what=""):
     fields = lbm.lb_read_fields(lat)
     ofields = orc.fields()
     errs = {"f": rel(f, of, fluid), "g": rel(g, og, fluid)}
-    for name, a, b in zip(("phi", "rho", "ux", "uy"), fields, ofields):
-        if np.abs(b[fluid]).max() > 0:
-            errs[name] = rel(a, b, fluid)
+    for name, a, b in zip(("phi", "rho"), fields[:2], ofields[:2]):
+        errs[name] = rel(a, b, fluid)
+    for name, a, b in zip(("ux", "uy"), fields[2:], ofields[2:]):
+        errs[name] = np.abs(a - b)[fluid].max()
     say(f"  {what}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= tol, (what, k, v)
@@ -92,8 +96,29 @@ def test_every_term_random_fields(collision, zf, zg):
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
 @pytest.mark.parametrize("theta", [30.0, 130.0])
 def test_c2_viscosity_ratio_10(collision, theta):
+    """BGK with tau = 0.55 in the phi = -1 phase is unstable in this model (the
+    oracle goes non-finite near step 600, also at uniform tau = 0.55), so BGK is
+    compared over the first 300 steps; MRT over 1000."""
     p, inp = wl.c2_drop(collision, analysis.theory_dphi(theta, 0.04, 0.04), seed=201)
-    run_pair(p, inp, 1000, what=f"C2 256x128 {collision} {theta}deg")
+    run_pair(p, inp, 1000 if collision == "mrt" else 300,
+             what=f"C2 256x128 {collision} {theta}deg")
+
+
+def test_c2_bgk_instability_reproduced_and_flagged():
+    """Both sides blow up on the BGK C2 case; the GPU reports it through the
+    periodic check as LB_ENUMERIC."""
+    p, inp = wl.c2_drop("bgk", analysis.theory_dphi(30.0, 0.04, 0.04), seed=201)
+    say("case C2 bgk instability")
+    orc = make_oracle(p, inp)
+    orc.step(1000)
+    assert not np.isfinite(orc.diagnostics()["kinetic"])
+    lat = lbm.lb_init(lbm.make_params(p, "f64", diag_every=100), inp["solid"], inp["phi0"],
+                      dphi=inp["dphi"], rho0=inp["rho0"])
+    lbm.lb_step(lat, 1000)
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_read_fields(lat)
+    assert e.value.code == lbm.LB_ENUMERIC
+    lat.close()
 
 
 def test_capillary_geometry_plate_ends():
@@ -182,11 +207,11 @@ def test_conservation_on_gpu():
 
 def test_contact_angle_matches_oracle_measurement():
     p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
-    say("case contact angle C1 3000 steps")
+    say("case contact angle C1 5000 steps")
     lat = gpu_lattice(p, inp, "f64")
     orc = make_oracle(p, inp)
-    lbm.lb_step(lat, 3000)
-    orc.step(3000)
+    lbm.lb_step(lat, 5000)
+    orc.step(5000)
     win = (0.0, 100.0, 3.5, 47.0)
     ca = lbm.lb_contact_angle(lat, *win, 0.5, 1)
     oca = analysis.contact_angle(orc.fields()[0], inp["solid"], 0.5, 1, *win)
