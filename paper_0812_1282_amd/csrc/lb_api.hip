@@ -53,14 +53,16 @@ Layout make_layout(int nx, int ny, int storage) {
     L.pitch = (int32_t)round_up((size_t)nx, kPitchAlign);
     L.plane = (int64_t)L.pitch * ny;
     const size_t plane = (size_t)L.plane;
+    const size_t pitch = (size_t)L.pitch;
     if (storage == ST_F64) {
-        L.buf_bytes = round_up(18 * plane * 8, 256);
+        L.row_bytes = 18 * pitch * 8;
     } else if (storage == ST_F32) {
-        L.buf_bytes = round_up(18 * plane * 4, 256);
+        L.row_bytes = 18 * pitch * 4;
     } else {
-        L.g0_offset = round_up(17 * plane * 2, 256);
-        L.buf_bytes = round_up(L.g0_offset + plane * 4, 256);
+        L.g0_offset = 17 * pitch * 2;
+        L.row_bytes = L.g0_offset + pitch * 4;
     }
+    L.buf_bytes = round_up(L.row_bytes * ny, 256);
     const size_t dsz = storage == ST_F64 ? 8 : 4;
     L.off_buf0 = 0;
     L.off_buf1 = L.buf_bytes;
@@ -149,6 +151,10 @@ int validate_params(const lb_params* p) {
         return fail(LB_EINVAL, "zero_u flags must be 0 or 1");
     if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
     if (p->reserved != 0) return fail(LB_EINVAL, "reserved must be 0");
+    // One row block of the populations is addressed through a buffer
+    // descriptor with a 32-bit record count.
+    if ((int64_t)((p->nx + 63) / 64) * 64 * 18 * 8 >= ((int64_t)1 << 31))
+        return fail(LB_EINVAL, "nx too large");
     return LB_OK;
 }
 
@@ -266,6 +272,7 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
     v.ny = ny;
     v.pitch = L.pitch;
     v.plane = L.plane;
+    v.row_bytes = (int64_t)L.row_bytes;
     v.g0_offset = (int64_t)L.g0_offset;
     v.buf[0] = mb.base + L.off_buf0;
     v.buf[1] = mb.base + L.off_buf1;
@@ -279,13 +286,11 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
     v.tau_alpha = p->tau_alpha;
     v.tau_beta = p->tau_beta;
     v.inv_tau_phi = 1.0 / p->tau_phi;
-    // Rest state of the model at rho_ref in either bulk phase (p0 is even in
-    // phi): f_i = w_i p0 for i >= 1 and f_0 = rho_ref - (5/3) p0.
-    const double p0 = p->rho_ref / 3.0 + 0.5 * p->A + 0.75 * p->B;
-    for (int i = 1; i < 9; ++i) v.ref[i] = (float)((i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * p0);
-    v.ref[0] = (float)(p->rho_ref - 5.0 / 3.0 * p0);
-    if (p->storage == LB_F64 || p->storage == LB_F32)
-        for (int i = 0; i < 9; ++i) v.ref[i] = 0.0f;
+    // Rest state of the model at rho_ref in either bulk phase phi = +-1 (p0 is
+    // even in phi): r_i = w_i p0 for i >= 1, r_0 = rho_ref - (5/3) p0. The
+    // formats other than FP64 store f_i - r_i.
+    v.rho_ref = p->rho_ref;
+    v.p0_ref = p->rho_ref / 3.0 + 0.5 * p->A + 0.75 * p->B;
     v.zero_u_feq = p->zero_u_feq;
     v.zero_u_geq = p->zero_u_geq;
     v.storage = p->storage;

@@ -9,11 +9,14 @@ namespace lbm {
 
 // ---------------------------------------------------------------------------
 // Device-memory layout of one lattice ("arena", one allocation):
-//   buf[0], buf[1]  population buffers (A/B ping-pong). Each holds the 18
-//                   planes f_0..f_8, g_0..g_8 of pitch*ny elements (row pitch
-//                   rounded up to 64 elements). In the 16-bit formats the
-//                   planes f_0..f_8, g_1..g_8 are 16-bit and g_0 is an FP32
-//                   plane placed after them.
+//   buf[0], buf[1]  population buffers (A/B ping-pong), row-interleaved: row y
+//                   is one block of row_bytes holding, one after another, the
+//                   pitch-long rows (pitch = nx rounded up to 64) of the 18
+//                   planes f_0..f_8, g_0..g_8. In the 16-bit formats the planes
+//                   f_0..f_8, g_1..g_8 are 16-bit (in that order) and g_0 is an
+//                   FP32 row at byte g0_offset of the block. Every format
+//                   except FP64 stores f_i - r_i, r_i the rest state at rho_ref
+//                   in a bulk phase.
 //   nbr             pitch*ny bytes. 0xFF marks a solid node; for a fluid node
 //                   bit (i-1) is set when the pull source r - e_i is solid.
 //   grec            pitch*ny bytes, used at solid nodes: bits 0..3 mark fluid
@@ -37,14 +40,15 @@ constexpr int kPartials = 8;        // doubles per workgroup partial record
 
 struct View {
     int32_t nx, ny, pitch, tiles_x;
-    int64_t plane;            // elements per population plane
-    int64_t g0_offset;        // byte offset of the FP32 g_0 plane (16-bit formats)
+    int64_t plane;            // nodes per plane including row padding (pitch * ny)
+    int64_t row_bytes;        // bytes of one row block of a population buffer
+    int64_t g0_offset;        // byte offset of the FP32 g_0 row inside a block (16-bit)
     char* buf[2];
     const uint8_t* nbr;
     const uint8_t* grec;
     const void* dphi;
     double A, B, kappa, Gamma, tau_alpha, tau_beta, inv_tau_phi;
-    float ref[9];             // rest-state shift of f (16-bit formats)
+    double rho_ref, p0_ref;   // rest state of the shifted formats: f_i - r_i is stored
     int32_t zero_u_feq, zero_u_geq;
     int32_t storage, collision;
 };
@@ -57,6 +61,7 @@ struct Tile {
 struct Layout {
     int32_t pitch;
     int64_t plane;
+    size_t row_bytes;       // bytes of one row block of a population buffer
     size_t buf_bytes;       // bytes of one population buffer
     size_t g0_offset;
     size_t off_buf0, off_buf1, off_nbr, off_grec, off_dphi, off_misc;

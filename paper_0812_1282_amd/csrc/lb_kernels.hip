@@ -12,10 +12,26 @@
 // ahead of the row being collided, with two halo columns on each side; the
 // pulled g of the two look-ahead rows stays in registers, so every g value is
 // loaded once for phi and reused by the collision.
+//
+// Addressing: for a row, every plane's row start is uniform across the
+// workgroup (kept in scalar registers) and each lane adds a 32-bit byte offset
+// for its column, so loads and stores use the global "scalar base + vector
+// offset" form. Bounce-back is a per-node fix-up after the regular pulls (only
+// nodes next to a wall take it).
+//
+// Arithmetic: FP64 for the FP64 format. The other formats store f_i - r_i, r_i
+// the rest state of a bulk phase at rho_ref, and do the FP32 arithmetic on
+// those deviations (rho - rho_ref, p0 - p0(rest), f^eq - r), which keeps the
+// small pressure differences that drive the interface (gamma / R) well above
+// FP32 rounding of O(1) quantities.
 #include "lb_internal.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
+
+#define GLOBAL __attribute__((address_space(1)))
 
 namespace lbm {
 
@@ -34,109 +50,205 @@ __device__ inline uint16_t float_to_bf16(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
+// Storage format traits. Plane p: 0..8 = f_0..f_8, 9..17 = g_0..g_8.
+//   E<p>    element type of plane p
+//   dec/enc conversion between a stored element and the working value
+// Working values of f planes are deviations f_i - r_i in the shifted formats.
+// The 16-bit formats keep f deviations times 2^6 and g_1..g_8 times 2^10, so
+// that the small values stay out of the FP16 subnormal range (powers of two:
+// the scaling itself is exact).
 template <int S>
-struct Pop;
+struct Fmt;
 
 template <>
-struct Pop<ST_F64> {
+struct Fmt<ST_F64> {
     using real = double;
-    static constexpr bool kShifted = false;
-    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
-        return reinterpret_cast<const double*>(b)[p * v.plane + i];
-    }
-    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
-        __builtin_nontemporal_store(x, reinterpret_cast<double*>(b) + p * v.plane + i);
-    }
+    static constexpr bool shifted = false;
+    template <int p> using E = double;
+    template <int p>
+    __device__ static int poff(const View& v) { return p * v.pitch * 8; }
+    template <int p>
+    __device__ static real dec(double x) { return x; }
+    template <int p>
+    __device__ static double enc(real x) { return x; }
 };
 
 template <>
-struct Pop<ST_F32> {
+struct Fmt<ST_F32> {
     using real = float;
-    static constexpr bool kShifted = false;
-    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
-        return reinterpret_cast<const float*>(b)[p * v.plane + i];
-    }
-    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
-        __builtin_nontemporal_store(x, reinterpret_cast<float*>(b) + p * v.plane + i);
-    }
+    static constexpr bool shifted = true;
+    template <int p> using E = float;
+    template <int p>
+    __device__ static int poff(const View& v) { return p * v.pitch * 4; }
+    template <int p>
+    __device__ static real dec(float x) { return x; }
+    template <int p>
+    __device__ static float enc(real x) { return x; }
 };
 
-// 16-bit formats: f_i stored as f_i - ref_i, g_1..g_8 stored as is, g_0 in FP32.
 template <int S>
-struct Pop16 {
+struct Fmt16 {
     using real = float;
-    static constexpr bool kShifted = true;
-    __device__ static float dec(uint16_t h) {
-        if constexpr (S == ST_F16S) {
-            _Float16 x = __builtin_bit_cast(_Float16, h);
-            return (float)x;
-        } else {
-            return bf16_to_float(h);
-        }
+    static constexpr bool shifted = true;
+    static constexpr float kF = 64.0f, kG = 1024.0f;
+    template <int p> using E = typename std::conditional<p == 9, float, uint16_t>::type;
+    template <int p>
+    __device__ static int poff(const View& v) {
+        if constexpr (p < 9) return p * v.pitch * 2;
+        else if constexpr (p == 9) return (int)v.g0_offset;
+        else return (p - 1) * v.pitch * 2;
     }
-    __device__ static uint16_t enc(float x) {
-        if constexpr (S == ST_F16S) {
-            _Float16 h = (_Float16)x;
-            return __builtin_bit_cast(uint16_t, h);
-        } else {
-            return float_to_bf16(x);
-        }
+    __device__ static float h2f(uint16_t h) {
+        if constexpr (S == ST_F16S) return (float)__builtin_bit_cast(_Float16, h);
+        else return bf16_to_float(h);
     }
-    // f planes return the stored deviation; pull() adds the shift.
-    __device__ static real ld(const char* b, const View& v, int p, int64_t i) {
-        const uint16_t* h = reinterpret_cast<const uint16_t*>(b);
-        if (p < 9) return dec(h[p * v.plane + i]);
-        if (p == 9) return reinterpret_cast<const float*>(b + v.g0_offset)[i];
-        return dec(h[(p - 1) * v.plane + i]);
+    __device__ static uint16_t f2h(float x) {
+        if constexpr (S == ST_F16S) return __builtin_bit_cast(uint16_t, (_Float16)x);
+        else return float_to_bf16(x);
     }
-    __device__ static void st(char* b, const View& v, int p, int64_t i, real x) {
-        uint16_t* h = reinterpret_cast<uint16_t*>(b);
-        if (p < 9) {
-            __builtin_nontemporal_store(enc(x - v.ref[p]), h + p * v.plane + i);
-        } else if (p == 9) {
-            __builtin_nontemporal_store(x, reinterpret_cast<float*>(b + v.g0_offset) + i);
-        } else {
-            __builtin_nontemporal_store(enc(x), h + (p - 1) * v.plane + i);
-        }
+    template <int p>
+    __device__ static real dec(E<p> x) {
+        if constexpr (p == 9) return x;
+        else if constexpr (p < 9) return h2f(x) * (1.0f / kF);
+        else return h2f(x) * (1.0f / kG);
+    }
+    template <int p>
+    __device__ static E<p> enc(real x) {
+        if constexpr (p == 9) return x;
+        else if constexpr (p < 9) return f2h(x * kF);
+        else return f2h(x * kG);
     }
 };
 template <>
-struct Pop<ST_F16S> : Pop16<ST_F16S> {};
+struct Fmt<ST_F16S> : Fmt16<ST_F16S> {};
 template <>
-struct Pop<ST_BF16S> : Pop16<ST_BF16S> {};
+struct Fmt<ST_BF16S> : Fmt16<ST_BF16S> {};
 
-// ------------------------------------------------------------------ helpers
+// Addressing. A row block of a population buffer is reached through a buffer
+// resource (base = the block, record count = its size, so the hardware
+// bounds-checks every access to that row); a plane inside the block is a
+// uniform scalar offset, and the column a 32-bit per-lane byte offset. Loads and
+// stores are then "buffer ... offen" with no per-lane 64-bit address math.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family GPUs
+
+__device__ inline Rsrc row_rsrc(const char* buf, const View& v, int y) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(buf + (size_t)y * v.row_bytes), 0,
+                                             (int)v.row_bytes, kRsrcWord3);
+}
+
+// Rows y, y-1, y+1 of the source buffer.
+struct Rows {
+    Rsrc r[3];
+};
+__device__ inline Rows rows_of(const char* buf, const View& v, int y, int ym, int yp) {
+    return Rows{{row_rsrc(buf, v, y), row_rsrc(buf, v, ym), row_rsrc(buf, v, yp)}};
+}
+
+// Per-lane byte offsets: columns x, x-1, x+1 of the main element size and
+// column x of plane 9 (g_0, FP32 in the 16-bit formats).
+struct ColOff {
+    uint32_t c[3];
+    uint32_t c9;
+};
+template <int S>
+__device__ inline ColOff col_offsets(uint32_t x, uint32_t xm, uint32_t xp) {
+    constexpr uint32_t sz = sizeof(typename Fmt<S>::template E<0>);
+    constexpr uint32_t sz9 = sizeof(typename Fmt<S>::template E<9>);
+    return ColOff{{x * sz, xm * sz, xp * sz}, x * sz9};
+}
+
+template <class E>
+__device__ inline E buf_ld(Rsrc r, uint32_t voff, int soff) {
+    if constexpr (sizeof(E) == 8)
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else if constexpr (sizeof(E) == 4)
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+
+template <class E>
+__device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
+    if constexpr (sizeof(E) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(unsigned int __attribute__((ext_vector_type(2))), x), r, voff, soff,
+            0);
+    else if constexpr (sizeof(E) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, voff, soff,
+                                              0);
+}
+
+// Plane p of the row behind r, at column selector c (0: x, 1: x-1, 2: x+1).
+template <int S, int p>
+__device__ inline typename Fmt<S>::real ldp(Rsrc r, const View& v, const ColOff& co, int c) {
+    using E = typename Fmt<S>::template E<p>;
+    const uint32_t voff = p == 9 ? co.c9 : co.c[c];
+    return Fmt<S>::template dec<p>(buf_ld<E>(r, voff, Fmt<S>::template poff<p>(v)));
+}
+
+template <int S, int p>
+__device__ inline void stp(Rsrc r, const View& v, const ColOff& co, typename Fmt<S>::real x) {
+    using E = typename Fmt<S>::template E<p>;
+    buf_st<E>(Fmt<S>::template enc<p>(x), r, p == 9 ? co.c9 : co.c[0],
+              Fmt<S>::template poff<p>(v));
+}
 
 __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Pull the nine populations of set `base` (0 = f, 9 = g) that arrive at fluid
-// node (x, y): from r - e_i, or, if that node is solid, the node's own
-// post-collision value in the opposite direction (mid-link bounce-back).
-template <int S>
-__device__ inline void pull(const char* src, const View& v, int base, int x, int xm, int xp,
-                            int64_t r0, int64_t rm, int64_t rp, uint32_t nb,
-                            typename Pop<S>::real out[9]) {
-    const int64_t self = r0 + x;
-    const int64_t from[9] = {self,   r0 + xm, r0 + xp, rm + x, rp + x,
-                             rm + xm, rp + xp, rm + xp, rp + xm};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const bool bb = (i > 0) && ((nb >> (i - 1)) & 1u);
-        out[i] = Pop<S>::ld(src, v, base + (bb ? OPP[i] : i), bb ? self : from[i]);
-        if constexpr (Pop<S>::kShifted) {
-            if (base == 0) out[i] += bb ? v.ref[OPP[i]] : v.ref[i];
-        }
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (N > 0) {
+        static_for<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
+
+// Pull the nine populations of set B (0 = f, 9 = g) arriving at fluid node
+// (x, y): from r - e_i, then, for links whose source is solid (bits of nb),
+// the node's own post-collision value in the opposite direction (mid-link
+// bounce-back). Working values (deviations for shifted f).
+template <int S, int B>
+__device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
+                             typename Fmt<S>::real out[9]) {
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
+        constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
+        out[i] = ldp<S, B + i>(R.r[r], v, co, c);
+    });
+    if (nb != 0u) {
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                if ((nb >> (i - 1)) & 1u) out[i] = ldp<S, B + OPP[i]>(R.r[0], v, co, 0);
+            }
+        });
     }
 }
 
 // ------------------------------------------------------------------ the sweep
 
+// Waves per SIMD the register allocator must leave room for (memory-level
+// parallelism of this bandwidth-bound sweep comes from resident waves).
+#ifndef LB_WAVES_F64
+#define LB_WAVES_F64 2
+#endif
+#ifndef LB_WAVES_F32
+#define LB_WAVES_F32 4
+#endif
+template <int S>
+constexpr int kWaves = S == ST_F64 ? LB_WAVES_F64 : LB_WAVES_F32;
+
 template <int S, int COLL, int BX, bool DIAG>
-__global__ __launch_bounds__(BX) void sweep_kernel(const View* __restrict__ views,
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
+void sweep_kernel(const View* __restrict__ views,
                                                    const Tile* __restrict__ tiles, int rows,
                                                    int parity, double* __restrict__ partials) {
-    using P = Pop<S>;
-    using real = typename P::real;
+    using F = Fmt<S>;
+    using real = typename F::real;
     constexpr int W = BX + 4;
     __shared__ real sphi[kNR][W];
 
@@ -150,249 +262,266 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const View* __restrict__ view
         tx = blockIdx.x;
         ty = blockIdx.y;
     }
-    const View v = views[member];  // kept in SGPRs for the whole strip
-    const int nx = v.nx, ny = v.ny, pitch = v.pitch;
-    // Select with ?: rather than indexing buf[] by a runtime value, which
-    // would force the View copy into private (scratch) memory.
-    const char* __restrict__ src = parity ? v.buf[1] : v.buf[0];
-    char* __restrict__ dst = parity ? v.buf[0] : v.buf[1];
-    const uint8_t* __restrict__ nbr = v.nbr;
+    const View v = views[member];  // uniform: lives in scalar registers
+    const int nx = v.nx, ny = v.ny;
+    // ?: rather than indexing buf[] by a runtime value (which would put the
+    // View copy in private memory).
+    const char* src = parity ? v.buf[1] : v.buf[0];
+    char* dst = parity ? v.buf[0] : v.buf[1];
 
     const int t = threadIdx.x;
     const int x0 = tx * BX;
     const int y0 = ty * rows;
     const int y1 = min(y0 + rows, ny);
-    const int xc = x0 + t;
-    const bool active = xc < nx;
-    const int x = xc % nx;
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
+    const bool active = x0 + t < nx;
+    // Lanes past the right edge compute phi of the wrapped columns the
+    // stencil of the last active columns needs.
+    const uint32_t x = (uint32_t)((x0 + t) % nx);
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1;
+    const uint32_t xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
     // Threads 0..3 also compute phi of the halo columns x0-2, x0-1, x0+BX, x0+BX+1.
     const bool halo = t < 4;
     const int hcol = t < 2 ? t : BX + t;
-    const int hx = ((x0 - 2 + hcol) % nx + nx) % nx;
-    const int hxm = hx == 0 ? nx - 1 : hx - 1;
-    const int hxp = hx == nx - 1 ? 0 : hx + 1;
+    const uint32_t hx = (uint32_t)(((x0 - 2 + hcol) % nx + nx) % nx);
+    const uint32_t hxm = hx == 0 ? nx - 1 : hx - 1;
+    const uint32_t hxp = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
 
     const real rA = (real)v.A, rB = (real)v.B, rK = (real)v.kappa, rG = (real)v.Gamma;
     const real ta = (real)v.tau_alpha, tb = (real)v.tau_beta, itp = (real)v.inv_tau_phi;
-    const real* __restrict__ dphi = reinterpret_cast<const real*>(v.dphi);
+    const real rApB = (real)(v.A + v.B);
+    const real rho_ref = (real)v.rho_ref;
+    const GLOBAL uint8_t* nbr = (const GLOBAL uint8_t*)v.nbr;
+    const GLOBAL uint8_t* grec = (const GLOBAL uint8_t*)v.grec;
+    const GLOBAL real* dphi = (const GLOBAL real*)v.dphi;
 
-    // phi of row yy into the ring; returns the pulled g of this thread's column.
-    auto phi_row = [&](int yy, real g[9], uint32_t& nb_out) {
-        const int y = wrap(yy, ny);
-        const int64_t r0 = (int64_t)y * pitch;
-        const int64_t rm = (int64_t)wrap(y - 1, ny) * pitch;
-        const int64_t rp = (int64_t)wrap(y + 1, ny) * pitch;
-        const uint32_t nb = nbr[r0 + x];
-        nb_out = nb;
+    const ColOff co = col_offsets<S>(x, xm, xp);
+    const ColOff hco = col_offsets<S>(hx, hxm, hxp);
+
+    // phi at the columns of `c` of the row behind R: pulls the nine g.
+    auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9]) -> real {
         real ph = 0;
         if (nb != 0xFFu) {
-            pull<S>(src, v, 9, x, xm, xp, r0, rm, rp, nb, g);
+            pull9<S, 9>(R, v, c, nb, g);
 #pragma unroll
             for (int i = 0; i < 9; ++i) ph += g[i];
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = 0;
         }
-        sphi[yy & (kNR - 1)][t + 2] = ph;
+        return ph;
+    };
+    // Fill ring row yy: this thread's column (pulled g returned) and the halo.
+    auto fill_row = [&](int yy, real g[9], uint32_t& nb) __attribute__((always_inline)) {
+        const int y = wrap(yy, ny);
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
+        nb = nrow[x];
+        sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g);
         if (halo) {
-            const uint32_t hnb = nbr[r0 + hx];
-            real hp = 0;
-            if (hnb != 0xFFu) {
-                real hg[9];
-                pull<S>(src, v, 9, hx, hxm, hxp, r0, rm, rp, hnb, hg);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) hp += hg[i];
-            }
-            sphi[yy & (kNR - 1)][hcol] = hp;
+            real hg[9];
+            sphi[yy & (kNR - 1)][hcol] = phi_of(R, nrow[hx], hco, hg);
         }
     };
 
-    real gA[9], gB[9], gN[9];
-    uint32_t nbA, nbB, nbN;
-    {
-        real gtmp[9];
-        uint32_t nbt;
-        phi_row(y0 - 2, gtmp, nbt);
-        phi_row(y0 - 1, gtmp, nbt);
-    }
-    phi_row(y0, gA, nbA);
-    phi_row(y0 + 1, gB, nbB);
+    double d_drho = 0.0, d_phi = 0.0, d_ke = 0.0, d_umax = 0.0, d_n = 0.0;
 
-    double d_rho = 0.0, d_phi = 0.0, d_ke = 0.0, d_umax = 0.0, d_n = 0.0;
-
-    for (int y = y0; y < y1; ++y) {
-        phi_row(y + 2, gN, nbN);
+    // One row: fill the ring two rows ahead (gnew), then collide row y (gc).
+    auto step = [&](int y, real gc[9], uint32_t nbc, real gnew[9],
+                    uint32_t& nbnew) __attribute__((always_inline)) {
+        fill_row(y + 2, gnew, nbnew);
         __syncthreads();
+        if (!active || nbc == 0xFFu) return;
+        const uint32_t nb = nbc;
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        real f[9];
+        pull9<S, 0>(R, v, co, nb, f);
 
-        if (active && nbA != 0xFFu) {
-            const uint32_t nb = nbA;
-            const int ym = wrap(y - 1, ny), yp = wrap(y + 1, ny);
-            const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch,
-                          rp = (int64_t)yp * pitch;
-            real f[9];
-            pull<S>(src, v, 0, x, xm, xp, r0, rm, rp, nb, f);
-
-            const int c = t + 2;
-            const real ph = sphi[y & (kNR - 1)][c];
-            // phi at the eight neighbours k = 1..8 (ghost values at solid ones).
-            real pn[9];
+        const int c = t + 2;
+        const real ph = sphi[y & (kNR - 1)][c];
+        // phi at the eight neighbours k = 1..8 (ghost values at solid ones).
+        real pn[9];
 #pragma unroll
-            for (int k = 1; k < 9; ++k) pn[k] = sphi[(y + EY[k]) & (kNR - 1)][c + EX[k]];
-            if (nb != 0u) {
+        for (int k = 1; k < 9; ++k) pn[k] = sphi[(y + EY[k]) & (kNR - 1)][c + EX[k]];
+        if (nb != 0u) {
 #pragma unroll
-                for (int k = 1; k < 9; ++k) {
-                    if ((nb >> (OPP[k] - 1)) & 1u) {
-                        // Solid neighbour s = r + e_k: mean of phi over its fluid
-                        // axis neighbours (else diagonal ones) minus the wall
-                        // gradient (times sqrt 2 across a diagonal).
-                        const int sy = wrap(y + EY[k], ny);
-                        const int sxw = EX[k] == 0 ? x : (EX[k] > 0 ? xp : xm);
-                        const int64_t s = (int64_t)sy * pitch + sxw;
-                        const uint32_t rec = v.grec[s];
-                        const real dw = dphi[s];
-                        real sum = 0;
-                        int cnt = 0;
-                        const uint32_t axis = rec & 0xFu;
-                        const int m0 = axis ? 1 : 5;
-                        const uint32_t bits = axis ? axis : (rec >> 4);
+            for (int k = 1; k < 9; ++k) {
+                if ((nb >> (OPP[k] - 1)) & 1u) {
+                    // Solid neighbour s = r + e_k: mean of phi over its fluid axis
+                    // neighbours (else diagonal ones) minus the wall gradient (times
+                    // sqrt 2 across a diagonal).
+                    const int sy = wrap(y + EY[k], ny);
+                    const uint32_t sxw = EX[k] == 0 ? x : (EX[k] > 0 ? xp : xm);
+                    const size_t s = (size_t)sy * v.pitch + sxw;
+                    const uint32_t rec = grec[s];
+                    const real dw = dphi[s];
+                    const uint32_t axis = rec & 0xFu;
+                    const int m0 = axis ? 1 : 5;
+                    const uint32_t bits = axis ? axis : (rec >> 4);
+                    real sum = 0;
+                    int cnt = 0;
 #pragma unroll
-                        for (int mm = 0; mm < 4; ++mm) {
-                            if ((bits >> mm) & 1u) {
-                                const int m = m0 + mm;
-                                sum += sphi[(y + EY[k] + EY[m]) & (kNR - 1)][c + EX[k] + EX[m]];
-                                ++cnt;
-                            }
+                    for (int mm = 0; mm < 4; ++mm) {
+                        if ((bits >> mm) & 1u) {
+                            const int m = m0 + mm;
+                            sum += sphi[(y + EY[k] + EY[m]) & (kNR - 1)][c + EX[k] + EX[m]];
+                            ++cnt;
                         }
-                        real gv = 0;
-                        if (cnt > 0)
-                            gv = sum / (real)cnt - (axis ? dw : (real)1.4142135623730951 * dw);
-                        pn[k] = gv;
                     }
+                    real gv = 0;
+                    if (cnt > 0)
+                        gv = sum / (real)cnt - (axis ? dw : (real)1.4142135623730951 * dw);
+                    pn[k] = gv;
                 }
             }
-            // Eq. (best): E = 1, W = 2, N = 3, S = 4, NE = 5, SW = 6, NW = 7, SE = 8.
-            const real gx = ((real)4 * (pn[1] - pn[2]) + (pn[5] - pn[7]) + (pn[8] - pn[6])) *
-                            (real)(1.0 / 12.0);
-            const real gy = ((real)4 * (pn[3] - pn[4]) + (pn[5] - pn[8]) + (pn[7] - pn[6])) *
-                            (real)(1.0 / 12.0);
-            const real lap = ((real)4 * (pn[1] + pn[2] + pn[3] + pn[4]) +
-                              (pn[5] + pn[6] + pn[7] + pn[8]) - (real)20 * ph) *
-                             (real)(1.0 / 6.0);
-
-            // Moments, Eq. (moments).
-            real rho = 0, jx = 0, jy = 0;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                rho += f[i];
-                jx += (real)EX[i] * f[i];
-                jy += (real)EY[i] * f[i];
-            }
-            const real ux = jx / rho, uy = jy / rho;
-
-            if constexpr (DIAG) {
-                const double u2 = (double)ux * ux + (double)uy * uy;
-                d_rho += rho;
-                d_phi += ph;
-                d_ke += 0.5 * (double)rho * u2;
-                const double um = sqrt(u2);
-                d_umax = (um > d_umax || um != um) ? um : d_umax;
-                d_n += 1.0;
-            }
-
-            // Eqs. (chempot), (p0), (tau).
-            const real mu = ph * (rA + rB * ph * ph) - rK * lap;
-            const real p0 = rho * (real)(1.0 / 3.0) + ph * ph * (rA * (real)0.5 + rB * (real)0.75 * ph * ph);
-            const real pc = ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph);
-            const real tau = tb + (real)0.5 * (pc + (real)1) * (ta - tb);
-            const real omega = (real)1 / tau;
-
-            // Step 2: u = 0 at boundary nodes in the equilibria (flags).
-            const bool bnd = nb != 0u;
-            const bool zf = bnd && v.zero_u_feq;
-            const bool zg = bnd && v.zero_u_geq;
-            const real ufx = zf ? (real)0 : ux, ufy = zf ? (real)0 : uy;
-            const real ugx = zg ? (real)0 : ux, ugy = zg ? (real)0 : uy;
-
-            // Appendix A, Eq. (equilibrium) for i = 1..8 and Eq. (feq0).
-            const real basef = p0 - rK * ph * lap;
-            const real gxx = rK * gx * gx, gyy = rK * gy * gy, gxy = rK * gx * gy;
-            const real usf = ufx * ufx + ufy * ufy;
-            const real usg = ugx * ugx + ugy * ugy;
-            const real baseg = rG * mu;
-            real feq[9], geq[9];
-            real sf = 0, sg = 0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const real w = i < 5 ? (real)(1.0 / 3.0) : (real)(1.0 / 12.0);
-                real wxx, wyy, wxy;
-                if (i < 3) {
-                    wxx = (real)(1.0 / 3.0); wyy = (real)(-1.0 / 6.0); wxy = 0;
-                } else if (i < 5) {
-                    wxx = (real)(-1.0 / 6.0); wyy = (real)(1.0 / 3.0); wxy = 0;
-                } else {
-                    wxx = (real)(-1.0 / 24.0); wyy = (real)(-1.0 / 24.0);
-                    wxy = i < 7 ? (real)0.25 : (real)-0.25;
-                }
-                const real euf = (real)EX[i] * ufx + (real)EY[i] * ufy;
-                const real eug = (real)EX[i] * ugx + (real)EY[i] * ugy;
-                feq[i] = w * (basef + rho * euf + (real)1.5 * rho * (euf * euf - usf * (real)(1.0 / 3.0))) +
-                         (wxx * gxx + wyy * gyy + wxy * gxy);
-                geq[i] = w * (baseg + ph * eug + (real)1.5 * ph * (eug * eug - usg * (real)(1.0 / 3.0)));
-                sf += feq[i];
-                sg += geq[i];
-            }
-            feq[0] = rho - sf;
-            geq[0] = ph - sg;
-
-            // Collision.
-            real fo[9];
-            if constexpr (COLL == CO_BGK) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) fo[i] = f[i] - omega * (f[i] - feq[i]);
-            } else {
-                // Eq. (mrtlb) with S = diag(0,1,1,0,1,0,1,w,w) written in moment space:
-                // f' = f^eq + (projection of f - f^eq on the conserved modes 0, 3, 5)
-                //      + (1 - w)(projection on the stress modes 7, 8),
-                // using the orthogonality of the rows of M (norms 9,36,36,6,12,6,12,4,4).
-                real d[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) d[i] = f[i] - feq[i];
-                const real m7 = (d[1] + d[2] - d[3] - d[4]) * (real)0.25 * ((real)1 - omega);
-                const real m8 = (d[5] + d[6] - d[7] - d[8]) * (real)0.25 * ((real)1 - omega);
-                // j - j^eq is zero unless Step 2 removed u from f^eq.
-                const real qx = zf ? jx * (real)(1.0 / 6.0) : (real)0;
-                const real qy = zf ? jy * (real)(1.0 / 6.0) : (real)0;
-                fo[0] = feq[0];
-                fo[1] = feq[1] + m7 + qx;
-                fo[2] = feq[2] + m7 - qx;
-                fo[3] = feq[3] - m7 + qy;
-                fo[4] = feq[4] - m7 - qy;
-                fo[5] = feq[5] + m8 + qx + qy;
-                fo[6] = feq[6] + m8 - qx - qy;
-                fo[7] = feq[7] - m8 - qx + qy;
-                fo[8] = feq[8] - m8 + qx - qy;
-            }
-            const int64_t self = r0 + x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) P::st(dst, v, i, self, fo[i]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) P::st(dst, v, 9 + i, self, gA[i] - itp * (gA[i] - geq[i]));
         }
+        // Eq. (best): E = 1, W = 2, N = 3, S = 4, NE = 5, SW = 6, NW = 7, SE = 8.
+        const real gx =
+            ((real)4 * (pn[1] - pn[2]) + (pn[5] - pn[7]) + (pn[8] - pn[6])) * (real)(1.0 / 12.0);
+        const real gy =
+            ((real)4 * (pn[3] - pn[4]) + (pn[5] - pn[8]) + (pn[7] - pn[6])) * (real)(1.0 / 12.0);
+        const real lap = ((real)4 * (pn[1] + pn[2] + pn[3] + pn[4]) +
+                          (pn[5] + pn[6] + pn[7] + pn[8]) - (real)20 * ph) *
+                         (real)(1.0 / 6.0);
+
+        // Moments, Eq. (moments): sums of the working values (deviations in the
+        // shifted formats, whose rest state has zero momentum and mass rho_ref).
+        real srho = 0, jx = 0, jy = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            gA[i] = gB[i];
-            gB[i] = gN[i];
+            srho += f[i];
+            jx += (real)EX[i] * f[i];
+            jy += (real)EY[i] * f[i];
         }
-        nbA = nbB;
-        nbB = nbN;
+        const real rho = F::shifted ? rho_ref + srho : srho;
+        const real inv_rho = (real)1 / rho;
+        const real ux = jx * inv_rho, uy = jy * inv_rho;
+
+        if constexpr (DIAG) {
+            const double u2 = (double)ux * ux + (double)uy * uy;
+            d_drho += F::shifted ? (double)srho : (double)srho - (double)v.rho_ref;
+            d_phi += ph;
+            d_ke += 0.5 * (double)rho * u2;
+            const double um = sqrt(u2);
+            d_umax = (um > d_umax || um != um) ? um : d_umax;
+            d_n += 1.0;
+        }
+
+        // Eqs. (chempot), (p0), (tau). In the shifted formats p0 is taken
+        // relative to its rest value and mu uses phi^2 - 1 = (phi - 1)(phi + 1).
+        real mu, basef;
+        if constexpr (F::shifted) {
+            const real q = (ph - (real)1) * (ph + (real)1);
+            mu = ph * (rB * q + rApB) - rK * lap;
+            const real dp0 = srho * (real)(1.0 / 3.0) +
+                             q * (rA * (real)0.5 + rB * (real)0.75 * (ph * ph + (real)1));
+            basef = dp0 - rK * ph * lap;
+        } else {
+            mu = ph * (rA + rB * ph * ph) - rK * lap;
+            const real p0 = rho * (real)(1.0 / 3.0) +
+                            ph * ph * (rA * (real)0.5 + rB * (real)0.75 * ph * ph);
+            basef = p0 - rK * ph * lap;
+        }
+        const real pc = ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph);
+        const real tau = tb + (real)0.5 * (pc + (real)1) * (ta - tb);
+        const real omega = (real)1 / tau;
+
+        // Step 2: u = 0 at boundary nodes in the equilibria (flags).
+        const bool bnd = nb != 0u;
+        const bool zf = bnd && v.zero_u_feq;
+        const bool zg = bnd && v.zero_u_geq;
+        const real ufx = zf ? (real)0 : ux, ufy = zf ? (real)0 : uy;
+        const real ugx = zg ? (real)0 : ux, ugy = zg ? (real)0 : uy;
+
+        // Appendix A, Eq. (equilibrium) for i = 1..8 and Eq. (feq0); in the
+        // shifted formats f^eq - r (r_i = w_i p0(rest)).
+        const real gxx = rK * gx * gx, gyy = rK * gy * gy, gxy = rK * gx * gy;
+        const real usf = ufx * ufx + ufy * ufy;
+        const real usg = ugx * ugx + ugy * ugy;
+        const real baseg = rG * mu;
+        real feq[9], geq[9];
+        real sf = 0, sg = 0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const real w = i < 5 ? (real)(1.0 / 3.0) : (real)(1.0 / 12.0);
+            real wxx, wyy, wxy;
+            if (i < 3) {
+                wxx = (real)(1.0 / 3.0); wyy = (real)(-1.0 / 6.0); wxy = 0;
+            } else if (i < 5) {
+                wxx = (real)(-1.0 / 6.0); wyy = (real)(1.0 / 3.0); wxy = 0;
+            } else {
+                wxx = (real)(-1.0 / 24.0); wyy = (real)(-1.0 / 24.0);
+                wxy = i < 7 ? (real)0.25 : (real)-0.25;
+            }
+            const real euf = (real)EX[i] * ufx + (real)EY[i] * ufy;
+            const real eug = (real)EX[i] * ugx + (real)EY[i] * ugy;
+            feq[i] = w * (basef + rho * euf + (real)1.5 * rho * (euf * euf - usf * (real)(1.0 / 3.0))) +
+                     (wxx * gxx + wyy * gyy + wxy * gxy);
+            geq[i] = w * (baseg + ph * eug + (real)1.5 * ph * (eug * eug - usg * (real)(1.0 / 3.0)));
+            sf += feq[i];
+            sg += geq[i];
+        }
+        feq[0] = srho - sf;  // rho - sum (absolute) or (rho - rho_ref) - sum (shifted)
+        geq[0] = ph - sg;
+
+        // Collision.
+        real fo[9];
+        if constexpr (COLL == CO_BGK) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fo[i] = f[i] - omega * (f[i] - feq[i]);
+        } else {
+            // Eq. (mrtlb) with S = diag(0,1,1,0,1,0,1,w,w) written in moment space:
+            // f' = f^eq + (projection of f - f^eq on the conserved modes 0, 3, 5)
+            //      + (1 - w)(projection on the stress modes 7, 8),
+            // from the orthogonality of the rows of M (norms 9,36,36,6,12,6,12,4,4).
+            real d[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = f[i] - feq[i];
+            const real m7 = (d[1] + d[2] - d[3] - d[4]) * (real)0.25 * ((real)1 - omega);
+            const real m8 = (d[5] + d[6] - d[7] - d[8]) * (real)0.25 * ((real)1 - omega);
+            // j - j^eq is zero unless Step 2 removed u from f^eq.
+            const real qx = zf ? jx * (real)(1.0 / 6.0) : (real)0;
+            const real qy = zf ? jy * (real)(1.0 / 6.0) : (real)0;
+            fo[0] = feq[0];
+            fo[1] = feq[1] + m7 + qx;
+            fo[2] = feq[2] + m7 - qx;
+            fo[3] = feq[3] - m7 + qy;
+            fo[4] = feq[4] - m7 - qy;
+            fo[5] = feq[5] + m8 + qx + qy;
+            fo[6] = feq[6] + m8 - qx - qy;
+            fo[7] = feq[7] - m8 - qx + qy;
+            fo[8] = feq[8] - m8 + qx - qy;
+        }
+        const Rsrc out = row_rsrc(dst, v, y);
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            stp<S, i>(out, v, co, fo[i]);
+            stp<S, 9 + i>(out, v, co, gc[i] - itp * (gc[i] - geq[i]));
+        });
+    };
+
+    real gA[9], gB[9], gC[9];
+    uint32_t nbA, nbB, nbC;
+    {
+        real gt[9];
+        uint32_t nbt;
+        fill_row(y0 - 2, gt, nbt);
+        fill_row(y0 - 1, gt, nbt);
+    }
+    fill_row(y0, gA, nbA);
+    fill_row(y0 + 1, gB, nbB);
+    // Unrolled by three so the three g rows rotate roles without copies.
+    for (int y = y0; y < y1; y += 3) {
+        step(y, gA, nbA, gC, nbC);
+        if (y + 1 >= y1) break;
+        step(y + 1, gB, nbB, gA, nbA);
+        if (y + 2 >= y1) break;
+        step(y + 2, gC, nbC, gB, nbB);
     }
 
     if constexpr (DIAG) {
         // Wavefront reduction, then across the BX/64 wavefronts in a fixed order.
         __shared__ double red[BX / 64][5];
-        double vals[5] = {d_rho, d_phi, d_ke, d_umax, d_n};
+        double vals[5] = {d_drho, d_phi, d_ke, d_umax, d_n};
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             double a = vals[k];
@@ -425,8 +554,11 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const View* __restrict__ view
             const int64_t rec = tiles ? (int64_t)blockIdx.x
                                       : (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
             double* out = partials + rec * kPartials;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) out[k] = o[k];
+            out[0] = o[0] + o[4] * v.rho_ref;  // sum rho = n rho_ref + sum (rho - rho_ref)
+            out[1] = o[1];
+            out[2] = o[2];
+            out[3] = o[3];
+            out[4] = o[4];
             out[5] = 0.0;
         }
     }
@@ -478,6 +610,34 @@ __global__ __launch_bounds__(256) void finalize_kernel(const int32_t* __restrict
     }
 }
 
+// ------------------------------------------------------------------ helpers for
+// the non-hot kernels: absolute FP64 values of a node's pulled populations.
+
+__device__ inline double rest_f(const View& v, int i) {
+    if (v.storage == ST_F64) return 0.0;
+    return i == 0 ? v.rho_ref - 5.0 / 3.0 * v.p0_ref : (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * v.p0_ref;
+}
+
+template <int S>
+__device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, double f[9],
+                                     double g[9]) {
+    const int nx = v.nx, ny = v.ny;
+    const uint32_t nb = v.nbr[(size_t)y * v.pitch + x];
+    if (nb == 0xFFu) return false;
+    const char* src = parity ? v.buf[1] : v.buf[0];
+    typename Fmt<S>::real a[9], b[9];
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+    const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
+    pull9<S, 0>(R, v, co, nb, a);
+    pull9<S, 9>(R, v, co, nb, b);
+    for (int i = 0; i < 9; ++i) {
+        f[i] = (double)a[i] + rest_f(v, i);
+        g[i] = (double)b[i];
+    }
+    return true;
+}
+
 // ------------------------------------------------------------------ initial state
 
 // S_0 = equilibria of the initial fields (ghost phi at solid nodes, stencils of
@@ -500,13 +660,12 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
     if (nb == 0xFFu) return;
     auto host_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * nx + wrap(xx, nx); };
     auto dev_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * pitch + wrap(xx, nx); };
-    const bool f64 = S == ST_F64;
     auto phi_at = [&](int xx, int yy) -> double {
         const int64_t s = dev_idx(xx, yy);
         if (v.nbr[s] != 0xFFu) return phi0[host_idx(xx, yy)];
         const uint32_t rec = v.grec[s];
-        const double dw = f64 ? reinterpret_cast<const double*>(v.dphi)[s]
-                              : (double)reinterpret_cast<const float*>(v.dphi)[s];
+        const double dw = S == ST_F64 ? reinterpret_cast<const double*>(v.dphi)[s]
+                                      : (double)reinterpret_cast<const float*>(v.dphi)[s];
         const uint32_t axis = rec & 0xFu;
         const uint32_t bits = axis ? axis : (rec >> 4);
         const int m0 = axis ? 1 : 5;
@@ -553,13 +712,22 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
     feq[0] = rho - sf;
     geq[0] = ph - sg;
     char* dst = v.buf[0];
-    for (int i = 0; i < 9; ++i) {
+    using R = typename Fmt<S>::real;
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
         const bool bb = i > 0 && ((nb >> (i - 1)) & 1u);
-        const int64_t at = bb ? r : dev_idx(x - EX[i], y - EY[i]);
-        const int pl = bb ? OPP[i] : i;
-        Pop<S>::st(dst, v, pl, at, (typename Pop<S>::real)feq[i]);
-        Pop<S>::st(dst, v, 9 + pl, at, (typename Pop<S>::real)geq[i]);
-    }
+        // Across a solid link the value waits at r in the opposite direction's plane.
+        const int xs = bb ? x : wrap(x - EX[i], nx), ys = bb ? y : wrap(y - EY[i], ny);
+        const Rsrc row = row_rsrc(dst, v, ys);
+        const ColOff co = col_offsets<S>((uint32_t)xs, (uint32_t)xs, (uint32_t)xs);
+        if (bb) {
+            stp<S, OPP[i]>(row, v, co, (R)(feq[i] - rest_f(v, OPP[i])));
+            stp<S, 9 + OPP[i]>(row, v, co, (R)geq[i]);
+        } else {
+            stp<S, i>(row, v, co, (R)(feq[i] - rest_f(v, i)));
+            stp<S, 9 + i>(row, v, co, (R)geq[i]);
+        }
+    });
 }
 
 // ------------------------------------------------------------------ read-back
@@ -572,28 +740,20 @@ __global__ __launch_bounds__(256) void moments_kernel(View v, int parity,
                                                       double* __restrict__ fields,
                                                       double* __restrict__ partials,
                                                       int32_t x_lo, int32_t x_hi) {
-    using real = typename Pop<S>::real;
     const int64_t n = (int64_t)v.nx * v.ny;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double a[6] = {0, 0, 0, 0, 0, 0};
     if (id < n) {
         const int x = (int)(id % v.nx), y = (int)(id / v.nx);
-        const int nx = v.nx, ny = v.ny;
-        const int64_t r0 = (int64_t)y * v.pitch, rm = (int64_t)wrap(y - 1, ny) * v.pitch,
-                      rp = (int64_t)wrap(y + 1, ny) * v.pitch;
-        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-        const uint32_t nb = v.nbr[r0 + x];
         double ph = 0, rho = 0, ux = 0, uy = 0;
-        if (nb != 0xFFu) {
-            real f[9], g[9];
-            pull<S>((parity ? v.buf[1] : v.buf[0]), v, 0, x, xm, xp, r0, rm, rp, nb, f);
-            pull<S>((parity ? v.buf[1] : v.buf[0]), v, 9, x, xm, xp, r0, rm, rp, nb, g);
+        double f[9], g[9];
+        if (pull_node_abs<S>(v, parity, x, y, f, g)) {
             double jx = 0, jy = 0;
             for (int i = 0; i < 9; ++i) {
-                rho += (double)f[i];
-                ph += (double)g[i];
-                jx += EX[i] * (double)f[i];
-                jy += EY[i] * (double)f[i];
+                rho += f[i];
+                ph += g[i];
+                jx += EX[i] * f[i];
+                jy += EY[i] * f[i];
             }
             ux = jx / rho;
             uy = jy / rho;
@@ -644,23 +804,18 @@ __global__ __launch_bounds__(256) void moments_kernel(View v, int parity,
 template <int S>
 __global__ __launch_bounds__(256) void read_plane_kernel(View v, int parity, int plane,
                                                          double* __restrict__ out) {
-    using real = typename Pop<S>::real;
     const int64_t n = (int64_t)v.nx * v.ny;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int x = (int)(id % v.nx), y = (int)(id / v.nx);
-    const int nx = v.nx, ny = v.ny;
-    const int64_t r0 = (int64_t)y * v.pitch, rm = (int64_t)wrap(y - 1, ny) * v.pitch,
-                  rp = (int64_t)wrap(y + 1, ny) * v.pitch;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const uint32_t nb = v.nbr[r0 + x];
-    if (nb == 0xFFu) {
+    double f[9], g[9];
+    if (!pull_node_abs<S>(v, parity, x, y, f, g)) {
         out[id] = 0.0;
         return;
     }
-    real p[9];
-    pull<S>((parity ? v.buf[1] : v.buf[0]), v, plane < 9 ? 0 : 9, x, xm, xp, r0, rm, rp, nb, p);
-    out[id] = (double)p[plane % 9];
+    double val = 0.0;
+    for (int i = 0; i < 9; ++i) val = (i == plane) ? f[i] : ((i == plane - 9) ? g[i] : val);
+    out[id] = val;
 }
 
 // phi = 0 crossings on the +x and +y links of every fluid node whose far end
@@ -670,23 +825,17 @@ __global__ __launch_bounds__(256) void crossings_kernel(View v, int parity,
                                                         Crossing* __restrict__ pts,
                                                         int64_t capacity,
                                                         unsigned long long* __restrict__ counter) {
-    using real = typename Pop<S>::real;
     const int64_t n = (int64_t)v.nx * v.ny;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int x = (int)(id % v.nx), y = (int)(id / v.nx);
     const int nx = v.nx, ny = v.ny;
     auto phi_at = [&](int xx, int yy, bool& fluid) -> double {
-        const int64_t r0 = (int64_t)yy * v.pitch, rm = (int64_t)wrap(yy - 1, ny) * v.pitch,
-                      rp = (int64_t)wrap(yy + 1, ny) * v.pitch;
-        const int xm = xx == 0 ? nx - 1 : xx - 1, xp = xx == nx - 1 ? 0 : xx + 1;
-        const uint32_t nb = v.nbr[r0 + xx];
-        fluid = nb != 0xFFu;
+        double f[9], g[9];
+        fluid = pull_node_abs<S>(v, parity, xx, yy, f, g);
         if (!fluid) return 0.0;
-        real g[9];
-        pull<S>((parity ? v.buf[1] : v.buf[0]), v, 9, xx, xm, xp, r0, rm, rp, nb, g);
         double s = 0;
-        for (int i = 0; i < 9; ++i) s += (double)g[i];
+        for (int i = 0; i < 9; ++i) s += g[i];
         return s;
     };
     bool fa;
