@@ -32,6 +32,8 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 74, "bf16s": 74}
 ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
+# Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
+DEFAULT_TILES = {"f64": (256, 64), "f32": (256, 32), "f16s": (256, 32), "bf16s": (256, 32)}
 
 
 def log(msg):
@@ -49,7 +51,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = auto)")
-    ap.add_argument("--tiles", default="", help="block_x,rows for every format (skip autotune)")
+    ap.add_argument("--tiles", default="", help="block_x,rows for every format")
+    ap.add_argument("--autotune", action="store_true", help="pick tiles with lb_autotune")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -85,6 +90,15 @@ def main():
 
     torch.cuda.set_device(0)
     lbm.load_library()
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {4 * n} bytes read and written once")
+        del a, b
+        torch.cuda.empty_cache()
     p, inp = wl.c4_drop()
     nx, ny = p["nx"], p["ny"]
     nodes = nx * ny
@@ -92,12 +106,13 @@ def main():
     results = {}
     for st in storages:
         lat = make_lattice(lbm, p, inp, st)
-        if args.tiles:
-            bx, rows = (int(v) for v in args.tiles.split(","))
+        if args.autotune:
+            tune = lbm.lb_autotune(lat, 10)
+        else:
+            bx, rows = ((int(v) for v in args.tiles.split(",")) if args.tiles
+                        else DEFAULT_TILES[st])
             lbm.lb_set_tuning(lat, bx, rows)
             tune = (bx, rows)
-        else:
-            tune = lbm.lb_autotune(lat, 10)
         ms, wall_ms = time_steps(torch, lbm, lat, args.steps, args.warmup)
         d = lbm.lb_diagnostics(lat, check=False)
         ms_step = ms / args.steps

@@ -59,9 +59,11 @@ extern "C" {
 #define LB_BGK 0
 #define LB_MRT 1
 
-/* Storage of the populations in device memory. Arithmetic is FP64 for
- * LB_F64 and FP32 for the others. LB_F16S / LB_BF16S store f_i minus a fixed
- * rest-state value and g_1..g_8 in 16 bits, and g_0 in FP32. */
+/* Storage of the populations in device memory. LB_F64 stores f and g in FP64
+ * and computes in FP64. The others compute in FP32 on deviations from the rest
+ * state of a bulk phase at rho_ref: LB_F32 stores f_i minus that rest value and
+ * g in FP32; LB_F16S / LB_BF16S store the f deviations and g_1..g_8 in 16 bits
+ * (scaled by powers of two) and g_0 in FP32. */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
@@ -198,6 +200,12 @@ const char* lb_last_error(void);
  * angle theta (degrees, 0..180) with mu = A phi + B phi^3 - kappa lap phi,
  * B = -A > 0. */
 int lb_dphi_for_angle(double theta_deg, double kappa, double A, double B, double* dphi);
+
+/* HBM ceiling of the device: time `repeats` streaming copies of `bytes`
+ * (>= 1 MiB) between two scratch buffers it allocates and frees, and return
+ * the read + write rate in GB/s. A reference for the sweep's achieved
+ * bandwidth, not part of the method. */
+int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs);
 
 /*
  * Batched ensembles: n independent lattices (own sizes, masks, parameters and

@@ -329,17 +329,23 @@ int check_tuning(int bx, int rows) {
 
 // Tile table of a batched group for the current tuning.
 int build_tiles(Group& g) {
-    std::vector<Tile> tiles;
+    std::vector<Tile> logical;
     std::vector<int32_t> first;
     for (size_t k = 0; k < g.m.size(); ++k) {
         const lb_params& p = g.m[k].p;
-        first.push_back((int32_t)tiles.size());
+        first.push_back((int32_t)logical.size());
         const int tx = (p.nx + g.block_x - 1) / g.block_x;
         const int ty = (p.ny + g.rows - 1) / g.rows;
         for (int j = 0; j < ty; ++j)
-            for (int i = 0; i < tx; ++i) tiles.push_back(Tile{(int32_t)k, i, j, first.back()});
+            for (int i = 0; i < tx; ++i)
+                logical.push_back(Tile{(int32_t)k, i, j, (int32_t)logical.size()});
     }
-    first.push_back((int32_t)tiles.size());
+    first.push_back((int32_t)logical.size());
+    // Workgroup b takes logical tile xcd_tile(b, n): members' neighbouring
+    // tiles stay on one XCD.
+    const int n = (int)logical.size();
+    std::vector<Tile> tiles(n);
+    for (int b = 0; b < n; ++b) tiles[b] = logical[xcd_tile(b, n)];
     if (tiles.size() > (size_t)g.n_tiles)
         return fail(LB_EINVAL, "tile table too small for this tuning");
     HIPCHK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
@@ -365,16 +371,18 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
         const int gx = (m0.p.nx + g.block_x - 1) / g.block_x;
         const int gy = (m0.p.ny + g.rows - 1) / g.rows;
         double* partials = reinterpret_cast<double*>(m0.base + L.off_partials);
-        hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag, m0.d_view,
-                                    nullptr, 0, gx, gy, g.rows, parity, partials, st);
+        hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
+                                    m0.p.tau_phi == 1.0, m0.d_view, nullptr, 0, gx, gy, g.rows,
+                                    parity, partials, st);
         if (e != hipSuccess || !diag) return e;
         return launch_finalize(nullptr, nullptr, 1, gx * gy, partials,
                                reinterpret_cast<double*>(m0.base + L.off_diag),
                                reinterpret_cast<int32_t*>(m0.base + L.off_flag), st);
     }
     const int nt = current_tiles(g);
-    hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag, g.d_views,
-                                g.d_tiles, nt, 0, 0, g.rows, parity, g.d_partials, st);
+    hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
+                                m0.p.tau_phi == 1.0, g.d_views, g.d_tiles, nt, 0, 0, g.rows,
+                                parity, g.d_partials, st);
     if (e != hipSuccess || !diag) return e;
     return launch_finalize(g.d_tiles, g.d_first, (int)g.m.size(), 0, g.d_partials, g.d_diag,
                            g.d_flag, st);
@@ -958,6 +966,51 @@ int lb_dphi_for_angle(double theta_deg, double kappa, double A, double B, double
     return LB_OK;
 }
 
+int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs) {
+    if (!gbs || repeats < 1 || bytes < (1u << 20)) return fail(LB_EINVAL, "need bytes >= 1 MiB, repeats >= 1");
+    bytes &= ~(size_t)255;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* a = nullptr;
+    char* b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return fail(LB_ENOMEM, "probe allocation failed");
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return fail(LB_ENOMEM, "probe allocation failed");
+    }
+    int rc = LB_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            rc = fail(LB_EHIP, "device query failed");
+            break;
+        }
+        const int blocks = cus * 16;
+        if (launch_fill(a, 1, bytes, st) != hipSuccess ||
+            launch_stream_copy(a, b, bytes, blocks, st) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+            hipEventRecord(e0, st) != hipSuccess) {
+            rc = fail(LB_EHIP, "probe launch failed");
+            break;
+        }
+        for (int r = 0; r < repeats && rc == LB_OK; ++r)
+            if (launch_stream_copy(a, b, bytes, blocks, st) != hipSuccess)
+                rc = fail(LB_EHIP, "probe launch failed");
+        float ms = 0;
+        if (rc == LB_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = fail(LB_EHIP, "probe timing failed");
+        if (rc == LB_OK) *gbs = 2.0 * (double)bytes * repeats / (ms * 1e-3) / 1e9;
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return rc;
+}
+
 // ---------------------------------------------------------------- batches
 
 int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
@@ -977,8 +1030,12 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
         if (rc) return fail(rc, "member " + std::to_string(k) + ": " + g_err);
         if (params[k].storage != params[0].storage || params[k].collision != params[0].collision ||
             params[k].zero_u_feq != params[0].zero_u_feq ||
-            params[k].zero_u_geq != params[0].zero_u_geq || params[k].diag_every != params[0].diag_every)
-            return fail(LB_EINVAL, "members must share storage, collision, Step 2 flags and diag_every");
+            params[k].zero_u_geq != params[0].zero_u_geq ||
+            params[k].diag_every != params[0].diag_every ||
+            (params[k].tau_phi == 1.0) != (params[0].tau_phi == 1.0))
+            return fail(LB_EINVAL,
+                        "members must share storage, collision, Step 2 flags, diag_every and "
+                        "whether tau_phi is 1");
     }
     int bx = 256, rows = 32;
     if (tuning) {

@@ -54,8 +54,19 @@ struct View {
 };
 
 struct Tile {
-    int32_t member, tx, ty, first;  // first: index of this member's first tile
+    int32_t member, tx, ty;
+    int32_t id;  // logical tile index (member-major, row-major): its partial-sum record
 };
+
+// XCD-aware order of workgroups: the device hands consecutive workgroup ids to
+// its 8 XCDs in turn, so workgroup b runs on XCD b % 8. Workgroup b is given
+// logical tile xcd_tile(b, n): each XCD receives one contiguous range of tiles
+// (row-major), so neighbouring tiles, which share halo cache lines, run at the
+// same time on the same XCD and share its L2.
+__host__ __device__ inline int xcd_tile(int b, int n) {
+    const int g = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return g * q + (g < r ? g : r) + k;
+}
 
 // Offsets of one lattice inside its arena.
 struct Layout {
@@ -75,9 +86,9 @@ Layout make_layout(int nx, int ny, int storage);
 
 // Kernel launchers (lb_kernels.hip). All enqueue on `stream` and return the
 // hipError_t of the launch.
-hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, const View* d_views,
-                        const Tile* d_tiles, int n_blocks_1d, int grid_x, int grid_y, int rows,
-                        int parity, double* partials, hipStream_t stream);
+hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool tau_phi_one,
+                        const View* d_views, const Tile* d_tiles, int n_blocks_1d, int grid_x,
+                        int grid_y, int rows, int parity, double* partials, hipStream_t stream);
 hipError_t launch_finalize(const Tile* d_tiles, const int32_t* member_first, int n_members,
                            int n_records_single, const double* partials, double* diag_out,
                            int32_t* flag, hipStream_t stream);
@@ -90,6 +101,8 @@ hipError_t launch_read_plane(const View& v, int parity, int plane, double* out,
 hipError_t launch_crossings(const View& v, int parity, void* points, int64_t capacity,
                             unsigned long long* counter, hipStream_t stream);
 hipError_t launch_fill(void* dst, uint8_t value, size_t bytes, hipStream_t stream);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
+                              hipStream_t stream);
 
 struct Crossing {
     uint64_t key;   // (node << 2) | (axis << 1) | (phi > 0 at the base node)

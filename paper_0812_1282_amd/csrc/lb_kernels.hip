@@ -168,17 +168,23 @@ __device__ inline E buf_ld(Rsrc r, uint32_t voff, int soff) {
         return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
 
+// Cache-policy bits of the population stores (0 = default).
+#ifndef LB_STORE_AUX
+#define LB_STORE_AUX 0
+#endif
+
 template <class E>
 __device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
     if constexpr (sizeof(E) == 8)
         __builtin_amdgcn_raw_buffer_store_b64(
             __builtin_bit_cast(unsigned int __attribute__((ext_vector_type(2))), x), r, voff, soff,
-            0);
+            LB_STORE_AUX);
     else if constexpr (sizeof(E) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff,
+                                              LB_STORE_AUX);
     else
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, voff, soff,
-                                              0);
+                                              LB_STORE_AUX);
 }
 
 // Plane p of the row behind r, at column selector c (0: x, 1: x-1, 2: x+1).
@@ -229,7 +235,50 @@ __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uin
     }
 }
 
-// ------------------------------------------------------------------ the sweep
+// phi = sum of the nine g pulled at (x, y), for callers that need only phi.
+// In the 16-bit formats the g_1..g_8 scale is applied once to their sum.
+template <int S>
+__device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const ColOff& co,
+                                             uint32_t nb) {
+    using F = Fmt<S>;
+    using real = typename F::real;
+    real gv[9];
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
+        constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
+        using E = typename F::template E<9 + i>;
+        const E e = buf_ld<E>(R.r[r], i == 0 ? co.c9 : co.c[c], F::template poff<9 + i>(v));
+        if constexpr (std::is_same<E, uint16_t>::value) gv[i] = F::h2f(e);
+        else gv[i] = (real)e;
+    });
+    if (nb != 0u) {
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                using E = typename F::template E<9 + OPP[i]>;
+                if ((nb >> (i - 1)) & 1u) {
+                    const E e = buf_ld<E>(R.r[0], co.c[0], F::template poff<9 + OPP[i]>(v));
+                    if constexpr (std::is_same<E, uint16_t>::value) gv[i] = F::h2f(e);
+                    else gv[i] = (real)e;
+                }
+            }
+        });
+    }
+    real s = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s += gv[i];
+    if constexpr (std::is_same<typename F::template E<10>, uint16_t>::value)
+        return gv[0] + s * (real)(1.0 / 1024.0);
+    else
+        return gv[0] + s;
+}
+
+template <class real>
+__device__ inline real recip(real x) {
+    if constexpr (std::is_same<real, float>::value) return __builtin_amdgcn_rcpf(x);
+    else return (real)1 / x;
+}
 
 // Waves per SIMD the register allocator must leave room for (memory-level
 // parallelism of this bandwidth-bound sweep comes from resident waves).
@@ -242,25 +291,28 @@ __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uin
 template <int S>
 constexpr int kWaves = S == ST_F64 ? LB_WAVES_F64 : LB_WAVES_F32;
 
-template <int S, int COLL, int BX, bool DIAG>
+// G1: tau_phi == 1 (the paper's choice for g), so g' = g^eq and the pulled g
+// are needed only for phi; they are then not kept in registers.
+template <int S, int COLL, int BX, bool DIAG, bool G1>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
-void sweep_kernel(const View* __restrict__ views,
-                                                   const Tile* __restrict__ tiles, int rows,
-                                                   int parity, double* __restrict__ partials) {
+void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles, int rows,
+                  int grid_x, int parity, double* __restrict__ partials) {
     using F = Fmt<S>;
     using real = typename F::real;
     constexpr int W = BX + 4;
     __shared__ real sphi[kNR][W];
 
-    int member = 0, tx, ty;
-    if (tiles) {
+    int member = 0, tx, ty, tile_id;
+    if (tiles) {  // batched members: the table is already in XCD-aware order
         const Tile tl = tiles[blockIdx.x];
         member = tl.member;
         tx = tl.tx;
         ty = tl.ty;
+        tile_id = tl.id;
     } else {
-        tx = blockIdx.x;
-        ty = blockIdx.y;
+        tile_id = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+        tx = tile_id % grid_x;
+        ty = tile_id / grid_x;
     }
     const View v = views[member];  // uniform: lives in scalar registers
     const int nx = v.nx, ny = v.ny;
@@ -273,6 +325,7 @@ void sweep_kernel(const View* __restrict__ views,
     const int x0 = tx * BX;
     const int y0 = ty * rows;
     const int y1 = min(y0 + rows, ny);
+    const int d = (ty & 1) ? -1 : 1;  // walking direction of this strip
     const bool active = x0 + t < nx;
     // Lanes past the right edge compute phi of the wrapped columns the
     // stencil of the last active columns needs.
@@ -297,20 +350,21 @@ void sweep_kernel(const View* __restrict__ views,
     const ColOff co = col_offsets<S>(x, xm, xp);
     const ColOff hco = col_offsets<S>(hx, hxm, hxp);
 
-    // phi at the columns of `c` of the row behind R: pulls the nine g.
+    // phi at the columns of `c` of the row behind R; the nine pulled g are
+    // returned in g unless G1.
     auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9]) -> real {
-        real ph = 0;
-        if (nb != 0xFFu) {
+        if (nb == 0xFFu) return (real)0;
+        if constexpr (G1) {
+            return phi9<S>(R, v, c, nb);
+        } else {
             pull9<S, 9>(R, v, c, nb, g);
+            real ph = 0;
 #pragma unroll
             for (int i = 0; i < 9; ++i) ph += g[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = 0;
+            return ph;
         }
-        return ph;
     };
-    // Fill ring row yy: this thread's column (pulled g returned) and the halo.
+    // Fill ring row yy: this thread's column and the halo columns.
     auto fill_row = [&](int yy, real g[9], uint32_t& nb) __attribute__((always_inline)) {
         const int y = wrap(yy, ny);
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
@@ -325,16 +379,20 @@ void sweep_kernel(const View* __restrict__ views,
 
     double d_drho = 0.0, d_phi = 0.0, d_ke = 0.0, d_umax = 0.0, d_n = 0.0;
 
-    // One row: fill the ring two rows ahead (gnew), then collide row y (gc).
+    // One row: fill the ring two rows ahead in the walking direction d
+    // (gnew), then collide row y (gc). The f pulls of row y are issued before
+    // the look-ahead g pulls are consumed, so both sets of loads are in flight
+    // together and each row waits for memory once.
     auto step = [&](int y, real gc[9], uint32_t nbc, real gnew[9],
                     uint32_t& nbnew) __attribute__((always_inline)) {
-        fill_row(y + 2, gnew, nbnew);
-        __syncthreads();
-        if (!active || nbc == 0xFFu) return;
+        const bool work = active && nbc != 0xFFu;
         const uint32_t nb = nbc;
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         real f[9];
-        pull9<S, 0>(R, v, co, nb, f);
+        if (work) pull9<S, 0>(R, v, co, nb, f);
+        fill_row(y + 2 * d, gnew, nbnew);
+        __syncthreads();
+        if (!work) return;
 
         const int c = t + 2;
         const real ph = sphi[y & (kNR - 1)][c];
@@ -355,15 +413,16 @@ void sweep_kernel(const View* __restrict__ views,
                     const uint32_t rec = grec[s];
                     const real dw = dphi[s];
                     const uint32_t axis = rec & 0xFu;
-                    const int m0 = axis ? 1 : 5;
                     const uint32_t bits = axis ? axis : (rec >> 4);
                     real sum = 0;
                     int cnt = 0;
 #pragma unroll
                     for (int mm = 0; mm < 4; ++mm) {
                         if ((bits >> mm) & 1u) {
-                            const int m = m0 + mm;
-                            sum += sphi[(y + EY[k] + EY[m]) & (kNR - 1)][c + EX[k] + EX[m]];
+                            // fluid neighbour s + e_m, m = mm + 1 (axis) or mm + 5 (diagonal)
+                            const int ex = axis ? EX[mm + 1] : EX[mm + 5];
+                            const int ey = axis ? EY[mm + 1] : EY[mm + 5];
+                            sum += sphi[(y + EY[k] + ey) & (kNR - 1)][c + EX[k] + ex];
                             ++cnt;
                         }
                     }
@@ -385,15 +444,11 @@ void sweep_kernel(const View* __restrict__ views,
 
         // Moments, Eq. (moments): sums of the working values (deviations in the
         // shifted formats, whose rest state has zero momentum and mass rho_ref).
-        real srho = 0, jx = 0, jy = 0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            srho += f[i];
-            jx += (real)EX[i] * f[i];
-            jy += (real)EY[i] * f[i];
-        }
+        const real srho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const real jx = (f[1] - f[2]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const real jy = (f[3] - f[4]) + (f[5] - f[6]) + (f[7] - f[8]);
         const real rho = F::shifted ? rho_ref + srho : srho;
-        const real inv_rho = (real)1 / rho;
+        const real inv_rho = recip(rho);
         const real ux = jx * inv_rho, uy = jy * inv_rho;
 
         if constexpr (DIAG) {
@@ -423,7 +478,7 @@ void sweep_kernel(const View* __restrict__ views,
         }
         const real pc = ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph);
         const real tau = tb + (real)0.5 * (pc + (real)1) * (ta - tb);
-        const real omega = (real)1 / tau;
+        const real omega = recip(tau);
 
         // Step 2: u = 0 at boundary nodes in the equilibria (flags).
         const bool bnd = nb != 0u;
@@ -432,36 +487,48 @@ void sweep_kernel(const View* __restrict__ views,
         const real ufx = zf ? (real)0 : ux, ufy = zf ? (real)0 : uy;
         const real ugx = zg ? (real)0 : ux, ugy = zg ? (real)0 : uy;
 
-        // Appendix A, Eq. (equilibrium) for i = 1..8 and Eq. (feq0); in the
-        // shifted formats f^eq - r (r_i = w_i p0(rest)).
+        // Appendix A, Eq. (equilibrium), evaluated for the pairs (e_i, -e_i):
+        // f^eq = even + odd and f^eq(-e) = even - odd, with the even part
+        // w [base + 3/2 rho ((e.u)^2 - |u|^2/3)] + gradient terms and the odd part
+        // w rho e.u; f^eq_0 from Eq. (feq0). Shifted formats: f^eq - r.
         const real gxx = rK * gx * gx, gyy = rK * gy * gy, gxy = rK * gx * gy;
-        const real usf = ufx * ufx + ufy * ufy;
-        const real usg = ugx * ugx + ugy * ugy;
-        const real baseg = rG * mu;
+        const real t3 = (real)(1.0 / 3.0), t12 = (real)(1.0 / 12.0);
         real feq[9], geq[9];
-        real sf = 0, sg = 0;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const real w = i < 5 ? (real)(1.0 / 3.0) : (real)(1.0 / 12.0);
-            real wxx, wyy, wxy;
-            if (i < 3) {
-                wxx = (real)(1.0 / 3.0); wyy = (real)(-1.0 / 6.0); wxy = 0;
-            } else if (i < 5) {
-                wxx = (real)(-1.0 / 6.0); wyy = (real)(1.0 / 3.0); wxy = 0;
-            } else {
-                wxx = (real)(-1.0 / 24.0); wyy = (real)(-1.0 / 24.0);
-                wxy = i < 7 ? (real)0.25 : (real)-0.25;
-            }
-            const real euf = (real)EX[i] * ufx + (real)EY[i] * ufy;
-            const real eug = (real)EX[i] * ugx + (real)EY[i] * ugy;
-            feq[i] = w * (basef + rho * euf + (real)1.5 * rho * (euf * euf - usf * (real)(1.0 / 3.0))) +
-                     (wxx * gxx + wyy * gyy + wxy * gxy);
-            geq[i] = w * (baseg + ph * eug + (real)1.5 * ph * (eug * eug - usg * (real)(1.0 / 3.0)));
-            sf += feq[i];
-            sg += geq[i];
+        real ev_x, ev_y, ev_p, ev_m;  // even parts of the pairs (1,2), (3,4), (5,6), (7,8)
+        {
+            const real usf = ufx * ufx + ufy * ufy;
+            const real bq = basef - (real)0.5 * rho * usf;  // base + 3/2 rho (0 - |u|^2/3)
+            const real r15 = (real)1.5 * rho;
+            const real upm = ufx + ufy, umm = ufy - ufx;
+            const real gd = (real)(1.0 / 24.0) * (gxx + gyy);
+            ev_x = t3 * (bq + r15 * ufx * ufx) + (t3 * gxx - (real)(1.0 / 6.0) * gyy);
+            ev_y = t3 * (bq + r15 * ufy * ufy) + (t3 * gyy - (real)(1.0 / 6.0) * gxx);
+            ev_p = t12 * (bq + r15 * upm * upm) - gd + (real)0.25 * gxy;
+            ev_m = t12 * (bq + r15 * umm * umm) - gd - (real)0.25 * gxy;
+            const real ox = t3 * rho * ufx, oy = t3 * rho * ufy;
+            const real op = t12 * rho * upm, om = t12 * rho * umm;
+            feq[1] = ev_x + ox; feq[2] = ev_x - ox;
+            feq[3] = ev_y + oy; feq[4] = ev_y - oy;
+            feq[5] = ev_p + op; feq[6] = ev_p - op;
+            feq[7] = ev_m + om; feq[8] = ev_m - om;
+            // rho - sum (absolute) or (rho - rho_ref) - sum (shifted)
+            feq[0] = srho - (real)2 * ((ev_x + ev_y) + (ev_p + ev_m));
         }
-        feq[0] = srho - sf;  // rho - sum (absolute) or (rho - rho_ref) - sum (shifted)
-        geq[0] = ph - sg;
+        {
+            const real usg = ugx * ugx + ugy * ugy;
+            const real bq = rG * mu - (real)0.5 * ph * usg;
+            const real p15 = (real)1.5 * ph;
+            const real upm = ugx + ugy, umm = ugy - ugx;
+            const real ex_ = t3 * (bq + p15 * ugx * ugx), ey_ = t3 * (bq + p15 * ugy * ugy);
+            const real ep_ = t12 * (bq + p15 * upm * upm), em_ = t12 * (bq + p15 * umm * umm);
+            const real ox = t3 * ph * ugx, oy = t3 * ph * ugy;
+            const real op = t12 * ph * upm, om = t12 * ph * umm;
+            geq[1] = ex_ + ox; geq[2] = ex_ - ox;
+            geq[3] = ey_ + oy; geq[4] = ey_ - oy;
+            geq[5] = ep_ + op; geq[6] = ep_ - op;
+            geq[7] = em_ + om; geq[8] = em_ - om;
+            geq[0] = ph - (real)2 * ((ex_ + ey_) + (ep_ + em_));
+        }
 
         // Collision.
         real fo[9];
@@ -473,11 +540,10 @@ void sweep_kernel(const View* __restrict__ views,
             // f' = f^eq + (projection of f - f^eq on the conserved modes 0, 3, 5)
             //      + (1 - w)(projection on the stress modes 7, 8),
             // from the orthogonality of the rows of M (norms 9,36,36,6,12,6,12,4,4).
-            real d[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] = f[i] - feq[i];
-            const real m7 = (d[1] + d[2] - d[3] - d[4]) * (real)0.25 * ((real)1 - omega);
-            const real m8 = (d[5] + d[6] - d[7] - d[8]) * (real)0.25 * ((real)1 - omega);
+            // Stress moments of f - f^eq: rows 7 (e_x^2 - e_y^2) and 8 (e_x e_y).
+            const real cw = (real)0.25 * ((real)1 - omega);
+            const real m7 = (((f[1] + f[2]) - (f[3] + f[4])) - (real)2 * (ev_x - ev_y)) * cw;
+            const real m8 = (((f[5] + f[6]) - (f[7] + f[8])) - (real)2 * (ev_p - ev_m)) * cw;
             // j - j^eq is zero unless Step 2 removed u from f^eq.
             const real qx = zf ? jx * (real)(1.0 / 6.0) : (real)0;
             const real qy = zf ? jy * (real)(1.0 / 6.0) : (real)0;
@@ -495,27 +561,34 @@ void sweep_kernel(const View* __restrict__ views,
         static_for<9>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             stp<S, i>(out, v, co, fo[i]);
-            stp<S, 9 + i>(out, v, co, gc[i] - itp * (gc[i] - geq[i]));
+            // Eq. (gevo); with tau_phi = 1 exactly g^eq.
+            stp<S, 9 + i>(out, v, co, G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]));
         });
     };
 
     real gA[9], gB[9], gC[9];
     uint32_t nbA, nbB, nbC;
+    // Odd strips walk downwards, so the two strips on either side of a strip
+    // boundary reach the rows they share (the halo of the phi stencil) at the
+    // same time and the second read hits in L2: vertical neighbours are
+    // gridDim.x workgroups apart and share an XCD when gridDim.x % 8 == 0.
+    const int nrow = y1 - y0;
+    const int ys = (d > 0) ? y0 : y1 - 1;
     {
         real gt[9];
         uint32_t nbt;
-        fill_row(y0 - 2, gt, nbt);
-        fill_row(y0 - 1, gt, nbt);
+        fill_row(ys - 2 * d, gt, nbt);
+        fill_row(ys - d, gt, nbt);
     }
-    fill_row(y0, gA, nbA);
-    fill_row(y0 + 1, gB, nbB);
+    fill_row(ys, gA, nbA);
+    fill_row(ys + d, gB, nbB);
     // Unrolled by three so the three g rows rotate roles without copies.
-    for (int y = y0; y < y1; y += 3) {
-        step(y, gA, nbA, gC, nbC);
-        if (y + 1 >= y1) break;
-        step(y + 1, gB, nbB, gA, nbA);
-        if (y + 2 >= y1) break;
-        step(y + 2, gC, nbC, gB, nbB);
+    for (int k = 0; k < nrow; k += 3) {
+        step(ys + k * d, gA, nbA, gC, nbC);
+        if (k + 1 >= nrow) break;
+        step(ys + (k + 1) * d, gB, nbB, gA, nbA);
+        if (k + 2 >= nrow) break;
+        step(ys + (k + 2) * d, gC, nbC, gB, nbB);
     }
 
     if constexpr (DIAG) {
@@ -551,9 +624,7 @@ void sweep_kernel(const View* __restrict__ views,
                 o[3] = (red[w][3] > o[3] || red[w][3] != red[w][3]) ? red[w][3] : o[3];
                 o[4] += red[w][4];
             }
-            const int64_t rec = tiles ? (int64_t)blockIdx.x
-                                      : (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-            double* out = partials + rec * kPartials;
+            double* out = partials + (int64_t)tile_id * kPartials;
             out[0] = o[0] + o[4] * v.rho_ref;  // sum rho = n rho_ref + sum (rho - rho_ref)
             out[1] = o[1];
             out[2] = o[2];
@@ -859,6 +930,23 @@ __global__ __launch_bounds__(256) void crossings_kernel(View v, int parity,
     }
 }
 
+// Streaming copy used to measure the HBM read+write ceiling of the device.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_copy_kernel(const f32x4* __restrict__ src,
+                                                          f32x4* __restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, stream,
+                       reinterpret_cast<const f32x4*>(src), reinterpret_cast<f32x4*>(dst),
+                       bytes / sizeof(f32x4));
+    return hipGetLastError();
+}
+
 __global__ void fill_kernel(uint8_t* __restrict__ p, uint8_t value, size_t bytes) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -867,20 +955,31 @@ __global__ void fill_kernel(uint8_t* __restrict__ p, uint8_t value, size_t bytes
 
 // ------------------------------------------------------------------ launchers
 
-template <int S, int C, int BX, bool D>
+// Passed from launch_sweep down the template dispatch (host side, per call).
+static thread_local bool g_tau_phi_one = false;
+
+template <int S, int C, int BX, bool D, bool G1>
 static hipError_t sweep_one(const View* views, const Tile* tiles, int n1d, int gx, int gy,
                             int rows, int parity, double* partials, hipStream_t st) {
-    const dim3 grid = tiles ? dim3(n1d) : dim3(gx, gy);
-    hipLaunchKernelGGL((sweep_kernel<S, C, BX, D>), grid, dim3(BX), 0, st, views, tiles, rows,
-                       parity, partials);
+    const dim3 grid = tiles ? dim3(n1d) : dim3(gx * gy);
+    hipLaunchKernelGGL((sweep_kernel<S, C, BX, D, G1>), grid, dim3(BX), 0, st, views, tiles,
+                       rows, gx, parity, partials);
     return hipGetLastError();
+}
+
+template <int S, int C, int BX, bool D>
+static hipError_t sweep_g(bool g1, const View* vw, const Tile* tl, int n1d, int gx, int gy,
+                          int rows, int par, double* parts, hipStream_t st) {
+    return g1 ? sweep_one<S, C, BX, D, true>(vw, tl, n1d, gx, gy, rows, par, parts, st)
+              : sweep_one<S, C, BX, D, false>(vw, tl, n1d, gx, gy, rows, par, parts, st);
 }
 
 template <int S, int C, int BX>
 static hipError_t sweep_d(bool diag, const View* vw, const Tile* tl, int n1d, int gx, int gy,
                           int rows, int par, double* parts, hipStream_t st) {
-    return diag ? sweep_one<S, C, BX, true>(vw, tl, n1d, gx, gy, rows, par, parts, st)
-                : sweep_one<S, C, BX, false>(vw, tl, n1d, gx, gy, rows, par, parts, st);
+    const bool g1 = g_tau_phi_one;
+    return diag ? sweep_g<S, C, BX, true>(g1, vw, tl, n1d, gx, gy, rows, par, parts, st)
+                : sweep_g<S, C, BX, false>(g1, vw, tl, n1d, gx, gy, rows, par, parts, st);
 }
 
 template <int S, int C>
@@ -901,9 +1000,10 @@ static hipError_t sweep_c(int coll, int bx, bool diag, const View* vw, const Til
                           : sweep_b<S, CO_BGK>(bx, diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
 }
 
-hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, const View* d_views,
-                        const Tile* d_tiles, int n_blocks_1d, int grid_x, int grid_y, int rows,
-                        int parity, double* partials, hipStream_t stream) {
+hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool tau_phi_one,
+                        const View* d_views, const Tile* d_tiles, int n_blocks_1d, int grid_x,
+                        int grid_y, int rows, int parity, double* partials, hipStream_t stream) {
+    g_tau_phi_one = tau_phi_one;
     switch (storage) {
         case ST_F64:
             return sweep_c<ST_F64>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,

@@ -28,7 +28,7 @@ EXPORTS = [
     "lb_get_tuning", "lb_autotune", "lb_get_step", "lb_free", "lb_last_error",
     "lb_dphi_for_angle", "lb_batch_init", "lb_batch_step", "lb_batch_read_fields",
     "lb_batch_read_populations", "lb_batch_contact_angle", "lb_batch_get_tuning",
-    "lb_batch_free",
+    "lb_batch_free", "lb_bandwidth_probe",
 ]
 
 
@@ -113,6 +113,7 @@ def load_library(path=LIB_PATH):
         "lb_batch_contact_angle": [_VP, i32, dbl, dbl, dbl, dbl, dbl, i32, _D],
         "lb_batch_get_tuning": [_VP, ctypes.POINTER(lb_tuning)],
         "lb_batch_free": [_VP],
+        "lb_bandwidth_probe": [ctypes.c_size_t, i32, _VP, _D],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -299,6 +300,14 @@ def lb_dphi_for_angle(theta_deg, kappa, A, B):
 
 def lb_free(lat):
     lat.close()
+
+
+def lb_bandwidth_probe(nbytes=1 << 30, repeats=20):
+    """Read + write GB/s of a streaming copy of nbytes on the current device."""
+    out = ctypes.c_double()
+    _check(load_library().lb_bandwidth_probe(int(nbytes), int(repeats), _torch_stream(),
+                                             ctypes.byref(out)))
+    return out.value
 
 
 # ------------------------------------------------------------------ batches
