@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 74, "bf16s": 74}
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 80, "bf16s": 80}
 ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.

@@ -62,8 +62,12 @@ extern "C" {
 /* Storage of the populations in device memory. LB_F64 stores f and g in FP64
  * and computes in FP64. The others compute in FP32 on deviations from the rest
  * state of a bulk phase at rho_ref: LB_F32 stores f_i minus that rest value and
- * g in FP32; LB_F16S / LB_BF16S store the f deviations and g_1..g_8 in 16 bits
- * (scaled by powers of two) and g_0 in FP32. */
+ * g in FP32; LB_F16S / LB_BF16S store the f_1..f_8 deviations and g_1..g_8 in
+ * 16 bits (scaled by powers of two) and the f_0 deviation and g_0 in 32 bits.
+ * In every shifted format g_0 is kept relative to the nearest of -1, 0, 1 and
+ * f_0, g_0 are formed from the rounded others, so that the stored populations
+ * of a node conserve rho and phi to FP32 precision of small values.
+ * Bytes per node per buffer: 144 (FP64), 72 (FP32), 40 (16-bit). */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
@@ -86,7 +90,10 @@ typedef struct {
     int32_t zero_u_feq;   /* Step 2 of Sec. VI: u = 0 at boundary nodes in f^eq */
     int32_t zero_u_geq;   /* the same for g^eq */
     int32_t diag_every;   /* enqueue the non-finite check every k steps (0 = never) */
-    int32_t reserved;     /* must be 0 */
+    int32_t tau_clamp;    /* 0: tau is Eq. (tau) in the node's phi, also where |phi| > 1;
+                             1: phi is clamped to [-1, 1] first, so tau stays between
+                             tau_beta and tau_alpha (keeps tau > 1/2 where phi
+                             overshoots a bulk value and that bulk tau is close to 1/2) */
 } lb_params;
 
 typedef struct {

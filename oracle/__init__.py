@@ -28,7 +28,8 @@ class OrcParams(ctypes.Structure):
                 ("tau_alpha", ctypes.c_double), ("tau_beta", ctypes.c_double),
                 ("tau_phi", ctypes.c_double),
                 ("collision", ctypes.c_int32),
-                ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32)]
+                ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32),
+                ("tau_clamp", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -88,12 +89,12 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, A=-0.04, B=0.04, kappa=0.04, Gamma=0.1, tau_alpha=1.0,
                 tau_beta=1.0, tau_phi=1.0, collision=BGK, zero_u_feq=None,
-                zero_u_geq=0):
+                zero_u_geq=0, tau_clamp=0):
     """Oracle parameters; Step 2 defaults to on for MRT and off for BGK."""
     if zero_u_feq is None:
         zero_u_feq = 1 if collision == MRT else 0
     return OrcParams(nx, ny, A, B, kappa, Gamma, tau_alpha, tau_beta, tau_phi,
-                     collision, zero_u_feq, zero_u_geq)
+                     collision, zero_u_feq, zero_u_geq, tau_clamp)
 
 
 class Oracle:

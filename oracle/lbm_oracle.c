@@ -27,8 +27,10 @@
  *    neighbours are diagonal uses the mean over those minus sqrt(2) d_perp phi.
  *  - a boundary node is a fluid node with at least one solid node among its
  *    eight lattice neighbours.
- *  - tau(phi) uses phi clamped to [-1, 1], so tau stays between the two bulk
- *    values.
+ *  - tau(phi) is the linear law of Eq. (tau) in the node's current phi, with
+ *    no clamp; both bulk values must exceed 1/2. An option (tau_clamp) clamps
+ *    phi to [-1, 1] first, for runs where phi overshoots a bulk value whose
+ *    tau is close to 1/2.
  *  - bounce-back applies to g as well as to f.
  *  - the stencil for d/dy is the printed d/dx stencil rotated by 90 degrees.
  */
@@ -204,10 +206,11 @@ void orc_gradients(int32_t nx, int32_t ny, const uint8_t* solid, const double* p
         }
 }
 
-/* Eq. (tau) with phi clamped to the bulk range. */
+/* Eq. (tau): linear in the node's phi; with tau_clamp, phi is first limited to
+ * the bulk range [-1, 1]. */
 double orc_tau(const orc_params* p, double phi) {
-    const double c = phi > 1.0 ? 1.0 : (phi < -1.0 ? -1.0 : phi);
-    return p->tau_beta + 0.5 * (c + 1.0) * (p->tau_alpha - p->tau_beta);
+    if (p->tau_clamp) phi = phi > 1.0 ? 1.0 : (phi < -1.0 ? -1.0 : phi);
+    return p->tau_beta + 0.5 * (phi + 1.0) * (p->tau_alpha - p->tau_beta);
 }
 
 /* Appendix A, Eqs. (equilibrium) and (feq0), with c = 1, and Eqs. (chempot), (p0)

@@ -42,6 +42,7 @@ typedef struct {
     int32_t collision;    /* 0 = BGK, 1 = MRT */
     int32_t zero_u_feq;   /* Step 2: u = 0 at boundary nodes in f^eq */
     int32_t zero_u_geq;   /* Step 2 applied to g^eq as well */
+    int32_t tau_clamp;    /* 1: phi clamped to [-1, 1] inside Eq. (tau); 0: the law as printed */
 } orc_params;
 
 typedef struct orc_state orc_state;

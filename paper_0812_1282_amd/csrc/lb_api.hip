@@ -59,7 +59,8 @@ Layout make_layout(int nx, int ny, int storage) {
     } else if (storage == ST_F32) {
         L.row_bytes = 18 * pitch * 4;
     } else {
-        L.g0_offset = 17 * pitch * 2;
+        // f_1..f_8, g_1..g_8 in 16 bits, then f_0 and g_0 in 32 bits
+        L.g0_offset = 16 * pitch * 2 + pitch * 4;
         L.row_bytes = L.g0_offset + pitch * 4;
     }
     L.buf_bytes = round_up(L.row_bytes * ny, 256);
@@ -150,7 +151,7 @@ int validate_params(const lb_params* p) {
     if ((p->zero_u_feq != 0 && p->zero_u_feq != 1) || (p->zero_u_geq != 0 && p->zero_u_geq != 1))
         return fail(LB_EINVAL, "zero_u flags must be 0 or 1");
     if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
-    if (p->reserved != 0) return fail(LB_EINVAL, "reserved must be 0");
+    if (p->tau_clamp != 0 && p->tau_clamp != 1) return fail(LB_EINVAL, "tau_clamp must be 0 or 1");
     // One row block of the populations is addressed through a buffer
     // descriptor with a 32-bit record count.
     if ((int64_t)((p->nx + 63) / 64) * 64 * 18 * 8 >= ((int64_t)1 << 31))
@@ -295,6 +296,7 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
     v.zero_u_geq = p->zero_u_geq;
     v.storage = p->storage;
     v.collision = p->collision;
+    v.tau_clamp = p->tau_clamp;
     mb.d_view = reinterpret_cast<View*>(mb.base + L.off_view);
     HIPCHK(hipMemcpyAsync(mb.d_view, &v, sizeof(View), hipMemcpyHostToDevice, st));
 

@@ -13,10 +13,11 @@ namespace lbm {
 //                   is one block of row_bytes holding, one after another, the
 //                   pitch-long rows (pitch = nx rounded up to 64) of the 18
 //                   planes f_0..f_8, g_0..g_8. In the 16-bit formats the planes
-//                   f_0..f_8, g_1..g_8 are 16-bit (in that order) and g_0 is an
-//                   FP32 row at byte g0_offset of the block. Every format
-//                   except FP64 stores f_i - r_i, r_i the rest state at rho_ref
-//                   in a bulk phase.
+//                   f_1..f_8, g_1..g_8 are 16-bit (in that order), followed by
+//                   32-bit rows of f_0 and g_0 (g_0 at byte g0_offset). Every
+//                   format except FP64 stores f_i - r_i, r_i the rest state at
+//                   rho_ref in a bulk phase, and g_0 split as b + q (G0Code in
+//                   the kernels).
 //   nbr             pitch*ny bytes. 0xFF marks a solid node; for a fluid node
 //                   bit (i-1) is set when the pull source r - e_i is solid.
 //   grec            pitch*ny bytes, used at solid nodes: bits 0..3 mark fluid
@@ -42,7 +43,8 @@ struct View {
     int32_t nx, ny, pitch, tiles_x;
     int64_t plane;            // nodes per plane including row padding (pitch * ny)
     int64_t row_bytes;        // bytes of one row block of a population buffer
-    int64_t g0_offset;        // byte offset of the FP32 g_0 row inside a block (16-bit)
+    int64_t g0_offset;        // byte offset of the 32-bit g_0 row inside a block (16-bit;
+                              // the 32-bit f_0 row precedes it)
     char* buf[2];
     const uint8_t* nbr;
     const uint8_t* grec;
@@ -51,6 +53,7 @@ struct View {
     double rho_ref, p0_ref;   // rest state of the shifted formats: f_i - r_i is stored
     int32_t zero_u_feq, zero_u_geq;
     int32_t storage, collision;
+    int32_t tau_clamp, pad_;
 };
 
 struct Tile {

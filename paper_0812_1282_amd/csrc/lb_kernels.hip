@@ -54,11 +54,36 @@ __device__ inline uint16_t float_to_bf16(float f) {  // round to nearest even
 //   E<p>    element type of plane p
 //   dec/enc conversion between a stored element and the working value
 // Working values of f planes are deviations f_i - r_i in the shifted formats.
-// The 16-bit formats keep f deviations times 2^6 and g_1..g_8 times 2^10, so
-// that the small values stay out of the FP16 subnormal range (powers of two:
-// the scaling itself is exact).
+// The 16-bit formats keep the f_1..f_8 deviations times 2^6 and g_1..g_8 times
+// 2^10, so that the small values stay out of the FP16 subnormal range (powers
+// of two: the scaling itself is exact); the f_0 deviation and g_0 are 32-bit.
 template <int S>
 struct Fmt;
+
+// g_0 in the shifted formats. g_0 is close to phi, i.e. to +-1 in a bulk phase,
+// where FP32 resolves only 6e-8: rounding it every step would create or destroy
+// phi at each node. It is therefore kept as g_0 = b + q with b in {-1, 0, 1}
+// and q small: q is an FP32 value rounded to nearest-even at 21 bits whose two
+// lowest significand bits hold b + 1. The sweep keeps b and the small sums
+// apart, so the stored g of a node add up to its phi to about 1e-9.
+struct G0Code {
+    __device__ static float q(uint32_t u) { return __builtin_bit_cast(float, u & ~3u); }
+    __device__ static float b(uint32_t u) { return (float)((int)(u & 3u) - 1); }
+    __device__ static uint32_t enc(float q, float b) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, q);
+        return ((u + 1u + ((u >> 2) & 1u)) & ~3u) | (uint32_t)((int)b + 1);
+    }
+    // Keep b while |q| <= 3/4 (no switching back and forth for a node at
+    // g_0 ~ +-1/2), else move b to the value nearest b + q.
+    __device__ static void rebase(float& q, float& b) {
+        if (__builtin_fabsf(q) > 0.75f) {
+            const float t = b + q;
+            const float nb = t > 0.5f ? 1.0f : (t < -0.5f ? -1.0f : 0.0f);
+            q += b - nb;
+            b = nb;
+        }
+    }
+};
 
 template <>
 struct Fmt<ST_F64> {
@@ -77,13 +102,19 @@ template <>
 struct Fmt<ST_F32> {
     using real = float;
     static constexpr bool shifted = true;
-    template <int p> using E = float;
+    template <int p> using E = typename std::conditional<p == 9, uint32_t, float>::type;
     template <int p>
     __device__ static int poff(const View& v) { return p * v.pitch * 4; }
     template <int p>
-    __device__ static real dec(float x) { return x; }
+    __device__ static real dec(E<p> x) {
+        static_assert(p != 9, "g_0 goes through G0Code");
+        return x;
+    }
     template <int p>
-    __device__ static float enc(real x) { return x; }
+    __device__ static E<p> enc(real x) {
+        static_assert(p != 9, "g_0 goes through G0Code");
+        return x;
+    }
 };
 
 template <int S>
@@ -91,12 +122,16 @@ struct Fmt16 {
     using real = float;
     static constexpr bool shifted = true;
     static constexpr float kF = 64.0f, kG = 1024.0f;
-    template <int p> using E = typename std::conditional<p == 9, float, uint16_t>::type;
+    template <int p>
+    using E = typename std::conditional<
+        p == 9, uint32_t, typename std::conditional<p == 0, float, uint16_t>::type>::type;
+    // Row block: f_1..f_8, g_1..g_8 (16-bit), then f_0 and g_0 (32-bit).
     template <int p>
     __device__ static int poff(const View& v) {
-        if constexpr (p < 9) return p * v.pitch * 2;
+        if constexpr (p == 0) return (int)v.g0_offset - v.pitch * 4;
+        else if constexpr (p < 9) return (p - 1) * v.pitch * 2;
         else if constexpr (p == 9) return (int)v.g0_offset;
-        else return (p - 1) * v.pitch * 2;
+        else return (p - 2) * v.pitch * 2;
     }
     __device__ static float h2f(uint16_t h) {
         if constexpr (S == ST_F16S) return (float)__builtin_bit_cast(_Float16, h);
@@ -108,13 +143,15 @@ struct Fmt16 {
     }
     template <int p>
     __device__ static real dec(E<p> x) {
-        if constexpr (p == 9) return x;
+        static_assert(p != 9, "g_0 goes through G0Code");
+        if constexpr (p == 0) return x;
         else if constexpr (p < 9) return h2f(x) * (1.0f / kF);
         else return h2f(x) * (1.0f / kG);
     }
     template <int p>
     __device__ static E<p> enc(real x) {
-        if constexpr (p == 9) return x;
+        static_assert(p != 9, "g_0 goes through G0Code");
+        if constexpr (p == 0) return x;
         else if constexpr (p < 9) return f2h(x * kF);
         else return f2h(x * kG);
     }
@@ -146,32 +183,42 @@ __device__ inline Rows rows_of(const char* buf, const View& v, int y, int ym, in
 }
 
 // Per-lane byte offsets: columns x, x-1, x+1 of the main element size and
-// column x of plane 9 (g_0, FP32 in the 16-bit formats).
+// column x of a 32-bit plane (f_0 and g_0 in the 16-bit formats; planes of a
+// size other than the main one are read and written at column x only).
 struct ColOff {
     uint32_t c[3];
     uint32_t c9;
 };
 template <int S>
 __device__ inline ColOff col_offsets(uint32_t x, uint32_t xm, uint32_t xp) {
-    constexpr uint32_t sz = sizeof(typename Fmt<S>::template E<0>);
+    constexpr uint32_t sz = sizeof(typename Fmt<S>::template E<1>);
     constexpr uint32_t sz9 = sizeof(typename Fmt<S>::template E<9>);
     return ColOff{{x * sz, xm * sz, xp * sz}, x * sz9};
 }
 
+// Cache-policy bits of the population loads and stores (bit 1 = nt, the
+// streaming hint). Stores are nontemporal: a post-collision population is read
+// again only in the next sweep, after the whole lattice has passed through the
+// caches, so keeping it there only displaces lines of rows still being pulled.
+#ifndef LB_LOAD_AUX
+#define LB_LOAD_AUX 0
+#endif
+#ifndef LB_STORE_AUX
+#define LB_STORE_AUX 2
+#endif
+
 template <class E>
 __device__ inline E buf_ld(Rsrc r, uint32_t voff, int soff) {
     if constexpr (sizeof(E) == 8)
-        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return __builtin_bit_cast(
+            E, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LB_LOAD_AUX));
     else if constexpr (sizeof(E) == 4)
-        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __builtin_bit_cast(
+            E, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LB_LOAD_AUX));
     else
-        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+        return __builtin_bit_cast(
+            E, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LB_LOAD_AUX));
 }
-
-// Cache-policy bits of the population stores (0 = default).
-#ifndef LB_STORE_AUX
-#define LB_STORE_AUX 0
-#endif
 
 template <class E>
 __device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
@@ -191,14 +238,16 @@ __device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
 template <int S, int p>
 __device__ inline typename Fmt<S>::real ldp(Rsrc r, const View& v, const ColOff& co, int c) {
     using E = typename Fmt<S>::template E<p>;
-    const uint32_t voff = p == 9 ? co.c9 : co.c[c];
+    constexpr bool wide = sizeof(E) != sizeof(typename Fmt<S>::template E<1>);
+    const uint32_t voff = wide ? co.c9 : co.c[c];
     return Fmt<S>::template dec<p>(buf_ld<E>(r, voff, Fmt<S>::template poff<p>(v)));
 }
 
 template <int S, int p>
 __device__ inline void stp(Rsrc r, const View& v, const ColOff& co, typename Fmt<S>::real x) {
     using E = typename Fmt<S>::template E<p>;
-    buf_st<E>(Fmt<S>::template enc<p>(x), r, p == 9 ? co.c9 : co.c[0],
+    constexpr bool wide = sizeof(E) != sizeof(typename Fmt<S>::template E<1>);
+    buf_st<E>(Fmt<S>::template enc<p>(x), r, wide ? co.c9 : co.c[0],
               Fmt<S>::template poff<p>(v));
 }
 
@@ -216,14 +265,25 @@ __device__ inline void static_for(F&& f) {
 // (x, y): from r - e_i, then, for links whose source is solid (bits of nb),
 // the node's own post-collision value in the opposite direction (mid-link
 // bounce-back). Working values (deviations for shifted f).
+// For g in the shifted formats out[0] is the small part q of g_0 and *base its
+// b (G0Code); otherwise *base is 0.
 template <int S, int B>
 __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
-                             typename Fmt<S>::real out[9]) {
+                             typename Fmt<S>::real out[9],
+                             typename Fmt<S>::real* base = nullptr) {
+    using F = Fmt<S>;
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
         constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
-        out[i] = ldp<S, B + i>(R.r[r], v, co, c);
+        if constexpr (B == 9 && i == 0 && F::shifted) {
+            const uint32_t u = buf_ld<uint32_t>(R.r[0], co.c9, F::template poff<9>(v));
+            out[0] = G0Code::q(u);
+            if (base) *base = G0Code::b(u);
+        } else {
+            out[i] = ldp<S, B + i>(R.r[r], v, co, c);
+            if (B == 9 && i == 0 && base) *base = 0;
+        }
     });
     if (nb != 0u) {
         static_for<9>([&](auto ic) {
@@ -236,10 +296,13 @@ __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uin
 }
 
 // phi = sum of the nine g pulled at (x, y), for callers that need only phi.
-// In the 16-bit formats the g_1..g_8 scale is applied once to their sum.
+// In the 16-bit formats the g_1..g_8 scale is applied once to their sum. In the
+// shifted formats phi = base + small, small = q + g_1 + ... + g_8 (G0Code); the
+// FP64 format returns small = phi, base = 0.
 template <int S>
 __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const ColOff& co,
-                                             uint32_t nb) {
+                                             uint32_t nb, typename Fmt<S>::real& small,
+                                             typename Fmt<S>::real& base) {
     using F = Fmt<S>;
     using real = typename F::real;
     real gv[9];
@@ -249,8 +312,14 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
         constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
         using E = typename F::template E<9 + i>;
         const E e = buf_ld<E>(R.r[r], i == 0 ? co.c9 : co.c[c], F::template poff<9 + i>(v));
-        if constexpr (std::is_same<E, uint16_t>::value) gv[i] = F::h2f(e);
-        else gv[i] = (real)e;
+        if constexpr (i == 0 && F::shifted) {
+            gv[0] = G0Code::q(e);
+            base = G0Code::b(e);
+        } else if constexpr (std::is_same<E, uint16_t>::value) {
+            gv[i] = Fmt16<S>::h2f(e);
+        } else {
+            gv[i] = (real)e;
+        }
     });
     if (nb != 0u) {
         static_for<9>([&](auto ic) {
@@ -259,7 +328,7 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
                 using E = typename F::template E<9 + OPP[i]>;
                 if ((nb >> (i - 1)) & 1u) {
                     const E e = buf_ld<E>(R.r[0], co.c[0], F::template poff<9 + OPP[i]>(v));
-                    if constexpr (std::is_same<E, uint16_t>::value) gv[i] = F::h2f(e);
+                    if constexpr (std::is_same<E, uint16_t>::value) gv[i] = Fmt16<S>::h2f(e);
                     else gv[i] = (real)e;
                 }
             }
@@ -269,9 +338,11 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
 #pragma unroll
     for (int i = 1; i < 9; ++i) s += gv[i];
     if constexpr (std::is_same<typename F::template E<10>, uint16_t>::value)
-        return gv[0] + s * (real)(1.0 / 1024.0);
+        small = gv[0] + s * (real)(1.0 / 1024.0);
     else
-        return gv[0] + s;
+        small = gv[0] + s;
+    if constexpr (!F::shifted) base = 0;
+    return F::shifted ? base + small : small;
 }
 
 template <class real>
@@ -352,28 +423,32 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
 
     // phi at the columns of `c` of the row behind R; the nine pulled g are
     // returned in g unless G1.
-    auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9]) -> real {
+    // (small, base): see phi9.
+    auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9], real& small,
+                      real& base) -> real {
+        small = 0;
+        base = 0;
         if (nb == 0xFFu) return (real)0;
         if constexpr (G1) {
-            return phi9<S>(R, v, c, nb);
+            return phi9<S>(R, v, c, nb, small, base);
         } else {
-            pull9<S, 9>(R, v, c, nb, g);
-            real ph = 0;
+            pull9<S, 9>(R, v, c, nb, g, &base);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) ph += g[i];
-            return ph;
+            for (int i = 0; i < 9; ++i) small += g[i];
+            return base + small;
         }
     };
     // Fill ring row yy: this thread's column and the halo columns.
-    auto fill_row = [&](int yy, real g[9], uint32_t& nb) __attribute__((always_inline)) {
+    auto fill_row = [&](int yy, real g[9], uint32_t& nb, real& small,
+                        real& base) __attribute__((always_inline)) {
         const int y = wrap(yy, ny);
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
         nb = nrow[x];
-        sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g);
+        sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, small, base);
         if (halo) {
-            real hg[9];
-            sphi[yy & (kNR - 1)][hcol] = phi_of(R, nrow[hx], hco, hg);
+            real hg[9], hs, hb;
+            sphi[yy & (kNR - 1)][hcol] = phi_of(R, nrow[hx], hco, hg, hs, hb);
         }
     };
 
@@ -383,14 +458,14 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     // (gnew), then collide row y (gc). The f pulls of row y are issued before
     // the look-ahead g pulls are consumed, so both sets of loads are in flight
     // together and each row waits for memory once.
-    auto step = [&](int y, real gc[9], uint32_t nbc, real gnew[9],
-                    uint32_t& nbnew) __attribute__((always_inline)) {
+    auto step = [&](int y, real gc[9], uint32_t nbc, real phs, real phb, real gnew[9],
+                    uint32_t& nbnew, real& snew, real& bnew) __attribute__((always_inline)) {
         const bool work = active && nbc != 0xFFu;
         const uint32_t nb = nbc;
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         real f[9];
         if (work) pull9<S, 0>(R, v, co, nb, f);
-        fill_row(y + 2 * d, gnew, nbnew);
+        fill_row(y + 2 * d, gnew, nbnew, snew, bnew);
         __syncthreads();
         if (!work) return;
 
@@ -454,7 +529,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         if constexpr (DIAG) {
             const double u2 = (double)ux * ux + (double)uy * uy;
             d_drho += F::shifted ? (double)srho : (double)srho - (double)v.rho_ref;
-            d_phi += ph;
+            d_phi += F::shifted ? (double)phb + (double)phs : (double)ph;
             d_ke += 0.5 * (double)rho * u2;
             const double um = sqrt(u2);
             d_umax = (um > d_umax || um != um) ? um : d_umax;
@@ -476,8 +551,8 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                             ph * ph * (rA * (real)0.5 + rB * (real)0.75 * ph * ph);
             basef = p0 - rK * ph * lap;
         }
-        const real pc = ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph);
-        const real tau = tb + (real)0.5 * (pc + (real)1) * (ta - tb);
+        const real pt = !v.tau_clamp ? ph : (ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph));
+        const real tau = tb + (real)0.5 * (pt + (real)1) * (ta - tb);
         const real omega = recip(tau);
 
         // Step 2: u = 0 at boundary nodes in the equilibria (flags).
@@ -558,16 +633,58 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             fo[8] = feq[8] - m8 + qx - qy;
         }
         const Rsrc out = row_rsrc(dst, v, y);
-        static_for<9>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            stp<S, i>(out, v, co, fo[i]);
-            // Eq. (gevo); with tau_phi = 1 exactly g^eq.
-            stp<S, 9 + i>(out, v, co, G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]));
-        });
+        if constexpr (S == ST_F16S || S == ST_BF16S) {
+            // Mass-preserving encoding: f_1..f_8 are rounded first and f_0 (a
+            // 32-bit deviation) is stored as the node's density deviation minus
+            // their rounded sum, so the stored populations add up to rho to FP32
+            // precision of a small value. (Collision conserves rho: the exact
+            // f'_0 is the same difference taken before rounding.)
+            using F = Fmt<S>;
+            float acc = 0.0f;
+            static_for<8>([&](auto ic) {
+                constexpr int i = decltype(ic)::value + 1;
+                const uint16_t h = F::f2h(fo[i] * F::kF);
+                acc += F::h2f(h);
+                buf_st<uint16_t>(h, out, co.c[0], F::template poff<i>(v));
+            });
+            buf_st<float>(srho - acc * (1.0f / F::kF), out, co.c9, F::template poff<0>(v));
+        } else {
+            static_for<9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                stp<S, i>(out, v, co, fo[i]);
+            });
+        }
+        if constexpr (F::shifted) {
+            // Eq. (gevo) for g_1..g_8 (with tau_phi = 1 exactly g^eq); g_0 is
+            // phi minus their stored sum, formed from the small parts (BGK for g
+            // conserves phi, so this is the exact g'_0).
+            real sg = 0;
+            static_for<8>([&](auto ic) {
+                constexpr int i = decltype(ic)::value + 1;
+                using E = typename F::template E<9 + i>;
+                const real gi = G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]);
+                const E e = F::template enc<9 + i>(gi);
+                if constexpr (std::is_same<E, uint16_t>::value) sg += Fmt16<S>::h2f(e);
+                else sg += e;
+                buf_st<E>(e, out, co.c[0], F::template poff<9 + i>(v));
+            });
+            if constexpr (std::is_same<typename F::template E<10>, uint16_t>::value)
+                sg *= (real)(1.0 / 1024.0);
+            real q = phs - sg, b = phb;
+            G0Code::rebase(q, b);
+            buf_st<uint32_t>(G0Code::enc(q, b), out, co.c9, F::template poff<9>(v));
+        } else {
+            static_for<9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                // Eq. (gevo); with tau_phi = 1 exactly g^eq.
+                stp<S, 9 + i>(out, v, co, G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]));
+            });
+        }
     };
 
     real gA[9], gB[9], gC[9];
     uint32_t nbA, nbB, nbC;
+    real sA, sB, sC, bA, bB, bC;  // phi = b + s of this column (see phi9)
     // Odd strips walk downwards, so the two strips on either side of a strip
     // boundary reach the rows they share (the halo of the phi stencil) at the
     // same time and the second read hits in L2: vertical neighbours are
@@ -575,20 +692,20 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const int nrow = y1 - y0;
     const int ys = (d > 0) ? y0 : y1 - 1;
     {
-        real gt[9];
+        real gt[9], st, bt;
         uint32_t nbt;
-        fill_row(ys - 2 * d, gt, nbt);
-        fill_row(ys - d, gt, nbt);
+        fill_row(ys - 2 * d, gt, nbt, st, bt);
+        fill_row(ys - d, gt, nbt, st, bt);
     }
-    fill_row(ys, gA, nbA);
-    fill_row(ys + d, gB, nbB);
+    fill_row(ys, gA, nbA, sA, bA);
+    fill_row(ys + d, gB, nbB, sB, bB);
     // Unrolled by three so the three g rows rotate roles without copies.
     for (int k = 0; k < nrow; k += 3) {
-        step(ys + k * d, gA, nbA, gC, nbC);
+        step(ys + k * d, gA, nbA, sA, bA, gC, nbC, sC, bC);
         if (k + 1 >= nrow) break;
-        step(ys + (k + 1) * d, gB, nbB, gA, nbA);
+        step(ys + (k + 1) * d, gB, nbB, sB, bB, gA, nbA, sA, bA);
         if (k + 2 >= nrow) break;
-        step(ys + (k + 2) * d, gC, nbC, gB, nbB);
+        step(ys + (k + 2) * d, gC, nbC, sC, bC, gB, nbB, sB, bB);
     }
 
     if constexpr (DIAG) {
@@ -696,16 +813,17 @@ __device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, do
     const uint32_t nb = v.nbr[(size_t)y * v.pitch + x];
     if (nb == 0xFFu) return false;
     const char* src = parity ? v.buf[1] : v.buf[0];
-    typename Fmt<S>::real a[9], b[9];
+    typename Fmt<S>::real a[9], b[9], base;
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
     const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
     pull9<S, 0>(R, v, co, nb, a);
-    pull9<S, 9>(R, v, co, nb, b);
+    pull9<S, 9>(R, v, co, nb, b, &base);
     for (int i = 0; i < 9; ++i) {
         f[i] = (double)a[i] + rest_f(v, i);
         g[i] = (double)b[i];
     }
+    g[0] += (double)base;  // exact: G0Code keeps g_0 = base + q
     return true;
 }
 
@@ -791,7 +909,16 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
         const int xs = bb ? x : wrap(x - EX[i], nx), ys = bb ? y : wrap(y - EY[i], ny);
         const Rsrc row = row_rsrc(dst, v, ys);
         const ColOff co = col_offsets<S>((uint32_t)xs, (uint32_t)xs, (uint32_t)xs);
-        if (bb) {
+        if constexpr (i == 0) {
+            stp<S, 0>(row, v, co, (R)(feq[0] - rest_f(v, 0)));
+            if constexpr (Fmt<S>::shifted) {
+                const double b = geq[0] > 0.5 ? 1.0 : (geq[0] < -0.5 ? -1.0 : 0.0);
+                buf_st<uint32_t>(G0Code::enc((float)(geq[0] - b), (float)b), row, co.c9,
+                                 Fmt<S>::template poff<9>(v));
+            } else {
+                stp<S, 9>(row, v, co, (R)geq[0]);
+            }
+        } else if (bb) {
             stp<S, OPP[i]>(row, v, co, (R)(feq[i] - rest_f(v, OPP[i])));
             stp<S, 9 + OPP[i]>(row, v, co, (R)geq[i]);
         } else {

@@ -1,0 +1,344 @@
+"""Workload drivers: run the paper's set-ups through the C ABI and report the
+quantities the paper measures (contact angle, spurious velocity, filling
+length, advancing angle), plus throughput.
+
+    python -m paper_0812_1282_amd.experiments c1|c2|c3|c4|c5 [--out results/x.json]
+
+c1  100 x 50 drop, BGK, equal viscosities, 60 degree wall (Sec. IV, Fig. 2(a))
+c2  256 x 128 drop, viscosity ratio 10, seven wall angles, BGK and MRT
+    (Sec. IV-VI, Fig. 2(b)); one batched launch per operator
+c3  capillary filling, 1024 x 64, viscosity ratio 1 and 10, MRT, FP32
+    (Sec. VII): l(t), advancing angle against capillary number, Washburn-type fit
+c4  4096 x 2048 drop, MRT, 90 degrees: FP32 and 16-bit shifted storage against
+    the FP64 run (max |d phi|, angle, sum of rho drift) at 10^4 and 2 x 10^4 steps
+c5  256-member ensemble, FP32 storage against an FP64 run of every member
+    (angle error and max |d phi| per member)
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import lbm
+from . import workloads as wl
+
+A_LANDAU = 0.04
+KAPPA = 0.04
+GAMMA_CONT = math.sqrt(8 * KAPPA * A_LANDAU / 9)  # sqrt(8 kappa a / 9), Sec. II
+
+
+def _torch():
+    import torch
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _dphi(theta):
+    return lbm.lb_dphi_for_angle(theta, KAPPA, -A_LANDAU, A_LANDAU)
+
+
+def _lattice(p, inp, storage="f64", **kw):
+    return lbm.lb_init(lbm.make_params(p, storage, **kw), inp["solid"], inp["phi0"],
+                       dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def spurious_near_contact(phi, ux, uy, solid, radius=5.0):
+    """Max |u| within `radius` of the phi = 0 crossings on the first fluid row
+    above the bottom wall, and the global max |u| over fluid nodes."""
+    speed = np.hypot(ux, uy)
+    fluid = solid == 0
+    row = phi[1]
+    xs = [x + row[x] / (row[x] - row[x + 1]) for x in range(len(row) - 1)
+          if fluid[1, x] and fluid[1, x + 1] and row[x] * row[x + 1] < 0]
+    ny, nx = phi.shape
+    y, x = np.mgrid[0:ny, 0:nx]
+    near = np.zeros_like(fluid)
+    for xc in xs:
+        near |= np.hypot(x - xc, y - 1.0) <= radius
+    near &= fluid
+    return {"contact_x": [round(v, 3) for v in xs],
+            "max_u_near_contact": float(speed[near].max()) if near.any() else None,
+            "max_u": float(speed[fluid].max())}
+
+
+def c1(steps=2000, extra=(5000, 10000)):
+    """The configured run (steps), then the same lattice continued to the step
+    counts in `extra` to show where the angle settles."""
+    torch = _torch()
+    p, inp = wl.c1_drop(seed=1, dphi_wall=_dphi(60.0))
+    lat = _lattice(p, inp)
+    d0 = lbm.lb_diagnostics(lat)
+    dt = _timed(torch, lambda: lbm.lb_step(lat, steps))
+    d1 = lbm.lb_diagnostics(lat)
+    ca = lbm.lb_contact_angle(lat, 0.0, 100.0, 3.5, 47.0, 0.5, 1)
+    res = {"workload": "C1 drop 100x50 BGK 60deg", "steps": steps,
+           "mlups": p["nx"] * p["ny"] * steps / dt / 1e6,
+           "theta": ca["theta"], "theta_target": 60.0, "radius": ca["R"],
+           "sum_rho": [d0["sum_rho"], d1["sum_rho"]], "sum_phi": [d0["sum_phi"], d1["sum_phi"]]}
+    later = []
+    for n in extra:
+        lbm.lb_step(lat, n - lbm.lb_get_step(lat))
+        later.append((n, lbm.lb_contact_angle(lat, 0.0, 100.0, 3.5, 47.0, 0.5, 1)["theta"]))
+    res["theta_later"] = later
+    lat.close()
+    return res
+
+
+def c2(steps=20000, every=2000):
+    torch = _torch()
+    angles = [30.0, 50.0, 70.0, 90.0, 110.0, 130.0, 150.0]
+    out = {"workload": "C2 drop 256x128 R=60, tau 0.55..1.0, FP64", "steps": steps, "runs": []}
+    for coll in ("bgk", "mrt"):
+        members, params = [], []
+        for th in angles:
+            p, inp = wl.c2_drop(coll, _dphi(th), seed=201)
+            members.append(inp)
+            params.append(lbm.make_params(p, "f64"))
+        b = lbm.lb_batch_init(params, members)
+        history = {th: [] for th in angles}
+        dead = {th: None for th in angles}
+        done = 0
+        t_run = 0.0
+        while done < steps:
+            n = min(every, steps - done)
+            t_run += _timed(torch, lambda: lbm.lb_batch_step(b, n))
+            done += n
+            for k, th in enumerate(angles):
+                if dead[th] is not None:
+                    continue
+                try:
+                    phi, rho, ux, uy = lbm.lb_batch_read_fields(b, k)
+                except lbm.LbError:
+                    phi = np.array([np.nan])
+                if not np.all(np.isfinite(phi)):
+                    dead[th] = done
+                    continue
+                try:
+                    th_m = lbm.lb_batch_contact_angle(b, k, 0.0, 256.0, 3.5, 124.0, 0.5, 1)
+                except lbm.LbError:
+                    th_m = None
+                history[th].append((done, th_m))
+        for k, th in enumerate(angles):
+            run = {"collision": coll, "theta_target": th, "history": history[th],
+                   "nonfinite_by_step": dead[th]}
+            if dead[th] is None:
+                phi, rho, ux, uy = lbm.lb_batch_read_fields(b, k)
+                run.update(spurious_near_contact(phi, ux, uy, members[k]["solid"]))
+                run["theta"] = history[th][-1][1] if history[th] else None
+                # R19: contact lines of neighbouring periodic images closer than 2W
+                xs = run["contact_x"]
+                if len(xs) >= 2:
+                    gap = 256.0 - (max(xs) - min(xs))
+                    run["image_gap"] = gap
+                    run["images_interact"] = gap < 2 * 2.83
+            out["runs"].append(run)
+        out[f"{coll}_mlups_batched"] = 7 * 256 * 128 * steps / t_run / 1e6
+        b.close()
+    return out
+
+
+def _meniscus_x(phi, x_lo, x_hi, row):
+    """First phi = 0 crossing from + to - along `row` in [x_lo, x_hi)."""
+    r = phi[row]
+    for x in range(max(x_lo, 0), x_hi - 1):
+        if r[x] > 0 >= r[x + 1]:
+            return x + r[x] / (r[x] - r[x + 1])
+    return None
+
+
+def c3(steps=100000, every=500, storage="f32", nx=1024, ny=64, ratios=(1, 10)):
+    torch = _torch()
+    res = {"workload": f"C3 capillary {nx}x{ny} MRT {storage}", "steps": steps, "runs": []}
+    for ratio in ratios:
+        p, inp = wl.c3_capillary(nx, ny, ratio, _dphi(60.0), seed=3)
+        x_in, x_out = nx // 2, (7 * nx) // 8
+        h = (ny - 1.5) - 0.5                       # wall planes at 0.5 and ny - 1.5
+        lat = _lattice(p, inp, storage)
+        rec = []
+        done = 0
+        t_run = 0.0
+        while done < steps:
+            t_run += _timed(torch, lambda: lbm.lb_step(lat, every))
+            done += every
+            l = lbm.lb_fill_length(lat, x_in, x_out, h)
+            phi = lbm.lb_read_fields(lat)[0]
+            xm = _meniscus_x(phi, x_in - 32, x_out, ny // 2)
+            th = None
+            if xm is not None and xm > x_in + 15 and xm < x_out - 15:
+                try:
+                    th = lbm.lb_contact_angle(lat, xm - 40.0, xm + 25.0, 3.5, ny - 4.5, 0.5,
+                                              1)["theta"]
+                except lbm.LbError:
+                    th = None
+            rec.append((done, l, xm, th))
+            if (xm is not None and xm > x_out - 10) or l > 0.97 * (x_out - x_in):
+                break
+        lat.close()
+        t = np.array([r[0] for r in rec], dtype=float)
+        l = np.array([r[1] for r in rec])
+        thetas = np.array([np.nan if r[3] is None else r[3] for r in rec])
+        nu_a = (p["tau_alpha"] - 0.5) / 3.0
+        nu_b = (p["tau_beta"] - 0.5) / 3.0
+        lc = float(x_out - x_in)
+        v = np.gradient(l, t) if len(l) > 2 else np.zeros_like(l)
+        ca = v * nu_a / GAMMA_CONT
+        # Two-fluid Washburn balance (Eq. (washburnlaw) with the displaced fluid's
+        # resistance): d/dt [nu_a l^2/2 + nu_b (Lc l - l^2/2)] = gamma h cos(theta_a)/6.
+        lhs = nu_a * l ** 2 / 2 + nu_b * (lc * l - l ** 2 / 2)
+        sel = (l > 0.15 * lc) & (l < 0.85 * lc) & np.isfinite(thetas)
+        fit = None
+        if sel.sum() >= 5:
+            slope = np.polyfit(t[sel], lhs[sel], 1)[0]
+            th_a = float(np.nanmean(thetas[sel]))
+            pred = GAMMA_CONT * h * math.cos(math.radians(th_a)) / 6.0
+            fit = {"slope": float(slope), "theta_a_mean": th_a,
+                   "predicted_slope_gamma_cont": pred, "ratio": float(slope / pred)}
+            good = sel & (ca > 0)
+            if good.sum() >= 3:
+                k, c0 = np.polyfit(ca[good], np.cos(np.radians(thetas[good])), 1)
+                fit["cos_theta_a_vs_Ca"] = {"slope": float(k), "intercept": float(c0),
+                                           "theta_a_at_Ca0": float(np.degrees(np.arccos(
+                                               np.clip(c0, -1, 1))))}
+        res["runs"].append({"ratio": ratio, "tau_alpha": p["tau_alpha"],
+                            "tau_beta": p["tau_beta"], "channel_width": h, "lc": lc,
+                            "mlups": nx * ny * done / t_run / 1e6,
+                            "records": [list(r) for r in rec], "fit": fit})
+    return res
+
+
+def c4(checkpoints=(10000, 20000), storages=("f32", "f16s", "bf16s")):
+    """Each storage format against the FP64 run of the same drop: max |d phi|
+    over fluid nodes, contact angle and relative drift of the sum of rho."""
+    torch = _torch()
+    p, inp = wl.c4_drop()
+    fluid = inp["solid"] == 0
+    win = (0.0, float(p["nx"]), 3.5, float(p["ny"]) - 4.0)
+    out = {"workload": "C4 drop 4096x2048 R=800 MRT 90deg", "checkpoints": list(checkpoints),
+           "runs": {}}
+    ref = {}
+
+    def run(storage):
+        lat = _lattice(p, inp, storage)
+        d0 = lbm.lb_diagnostics(lat)
+        rec, done, t_run = {}, 0, 0.0
+        for n in checkpoints:
+            t_run += _timed(torch, lambda: lbm.lb_step(lat, n - done))
+            done = n
+            d = lbm.lb_diagnostics(lat, check=False)
+            try:
+                th = lbm.lb_contact_angle(lat, *win, 0.5, 1)["theta"]
+            except lbm.LbError:
+                th = None
+            rec[n] = (lbm.lb_read_fields(lat)[0], th,
+                      abs(d["sum_rho"] - d0["sum_rho"]) / d0["sum_rho"])
+        lat.close()
+        torch.cuda.empty_cache()
+        return rec, p["nx"] * p["ny"] * done / t_run / 1e6
+
+    ref, mlups = run("f64")
+    out["runs"]["f64"] = {"mlups": mlups,
+                          "theta": {n: ref[n][1] for n in checkpoints},
+                          "rho_drift": {n: ref[n][2] for n in checkpoints}}
+    for st in storages:
+        rec, mlups = run(st)
+        r = {"mlups": mlups, "speedup_vs_f64": mlups / out["runs"]["f64"]["mlups"]}
+        for n in checkpoints:
+            dphi = np.abs(rec[n][0] - ref[n][0])[fluid]
+            th, th_ref = rec[n][1], ref[n][1]
+            r[str(n)] = {"max_dphi": float(np.nanmax(dphi)) if np.isfinite(dphi).all() else None,
+                         "theta": th,
+                         "dtheta": None if th is None or th_ref is None else abs(th - th_ref),
+                         "rho_drift": rec[n][2]}
+        out["runs"][st] = r
+        print(st, json.dumps(r, default=float), flush=True)
+    return out
+
+
+def c5(steps=10000, sample=None):
+    """Every member in FP32 (the ensemble's storage) and in FP64, both batched;
+    per member the angle difference and max |d phi| over fluid nodes."""
+    torch = _torch()
+    descs = wl.c5_instances()
+    if sample:
+        descs = descs[:sample]
+    members, p32, p64 = [], [], []
+    for d in descs:
+        p, inp = wl.c5_member(d, _dphi(d["theta"]))
+        members.append(inp)
+        p32.append(lbm.make_params(p, "f32"))
+        p64.append(lbm.make_params(p, "f64"))
+    nodes = sum(q.nx * q.ny for q in p32)
+    out = {"workload": f"C5 ensemble of {len(descs)} drops, MRT", "steps": steps, "nodes": nodes}
+    batches = {}
+    for name, params in (("f32", p32), ("f64", p64)):
+        b = lbm.lb_batch_init(params, members)
+        dt = _timed(torch, lambda: lbm.lb_batch_step(b, steps))
+        out[f"{name}_mlups"] = nodes * steps / dt / 1e6
+        out[f"{name}_tuning"] = list(lbm.lb_batch_get_tuning(b))
+        batches[name] = b
+    rows = []
+    for k, d in enumerate(descs):
+        row = {"nx": d["nx"], "theta_target": d["theta"], "ratio": d["ratio"]}
+        phis = {}
+        for name, b in batches.items():
+            try:
+                row[f"theta_{name}"] = lbm.lb_batch_contact_angle(
+                    b, k, 0.0, float(d["nx"]), 3.5, d["ny"] - 4.0, 0.5, 1)
+            except lbm.LbError as e:
+                row[f"theta_{name}"] = None
+                row[f"error_{name}"] = str(e)
+            phis[name] = lbm.lb_batch_read_fields(b, k)[0]
+        fl = members[k]["solid"] == 0
+        dphi = np.abs(phis["f32"] - phis["f64"])[fl]
+        row["max_dphi"] = float(dphi.max()) if np.isfinite(dphi).all() else None
+        if row["theta_f32"] is not None and row["theta_f64"] is not None:
+            row["dtheta"] = abs(row["theta_f32"] - row["theta_f64"])
+        rows.append(row)
+    for b in batches.values():
+        b.close()
+    dth = np.array([r.get("dtheta", np.nan) for r in rows])
+    dph = np.array([np.nan if r["max_dphi"] is None else r["max_dphi"] for r in rows])
+    out["max_dtheta_f32_vs_f64"] = float(np.nanmax(dth))
+    out["members_over_0p5deg"] = int(np.sum(dth > 0.5))
+    out["members_without_angle"] = int(np.sum(~np.isfinite(dth)))
+    out["max_dphi_f32_vs_f64"] = float(np.nanmax(dph))
+    out["members_over_1e-3_dphi"] = int(np.sum(dph > 1e-3))
+    out["members_nonfinite"] = int(np.sum(~np.isfinite(dph)))
+    out["members"] = rows
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--out", default="")
+    ap.add_argument("--steps", type=int, default=0)
+    args = ap.parse_args(argv)
+    fn = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}[args.which]
+    if not args.steps:
+        res = fn()
+    else:
+        res = fn((args.steps,)) if args.which == "c4" else fn(args.steps)
+    text = json.dumps(res, default=float)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text[:2000], flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -46,7 +46,7 @@ class lb_params(ctypes.Structure):
                 ("tau_phi", ctypes.c_double), ("rho_ref", ctypes.c_double),
                 ("collision", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32),
-                ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("diag_every", ctypes.c_int32), ("tau_clamp", ctypes.c_int32)]
 
 
 class lb_diag(ctypes.Structure):
@@ -153,7 +153,8 @@ def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0,
     return lb_params(p["nx"], p["ny"], p["A"], p["B"], p["kappa"], p["Gamma"],
                      p["tau_alpha"], p["tau_beta"], p["tau_phi"], p.get("rho_ref", 1.0),
                      coll, STORAGE[storage] if isinstance(storage, str) else int(storage),
-                     int(zero_u_feq), int(zero_u_geq), int(diag_every), 0)
+                     int(zero_u_feq), int(zero_u_geq), int(diag_every),
+                     int(p.get("tau_clamp", 0)))
 
 
 def _torch_stream():

@@ -183,5 +183,8 @@ def c5_instances(n=256, seed=5):
 
 
 def c5_member(desc, dphi_wall):
-    p = params(desc["nx"], desc["ny"], 1.0, desc["tau_beta"], "mrt")
+    """One ensemble member. tau(phi) clamps phi to [-1, 1]: with tau_beta as low
+    as 0.505, the overshoot of phi to about -1.12 next to a non-wetting wall
+    would take the unclamped law below 1/2."""
+    p = params(desc["nx"], desc["ny"], 1.0, desc["tau_beta"], "mrt", tau_clamp=1)
     return p, drop_on_wall(p, 0.4 * desc["ny"], desc["nx"] / 2.0, 0.0, desc["seed"], dphi_wall)

@@ -12,7 +12,8 @@ def orc_params(p, **over):
                               tau_beta=q["tau_beta"], tau_phi=q["tau_phi"],
                               collision=COLL[q["collision"]],
                               zero_u_feq=q.get("zero_u_feq"),
-                              zero_u_geq=q.get("zero_u_geq", 0))
+                              zero_u_geq=q.get("zero_u_geq", 0),
+                              tau_clamp=q.get("tau_clamp", 0))
 
 
 def make_oracle(p, inp, **over):

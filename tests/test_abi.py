@@ -45,7 +45,7 @@ def test_default_params_and_workspace():
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 2), ("ny", 0), ("tau_alpha", 0.5), ("tau_beta", 0.3), ("tau_phi", 0.5),
-    ("collision", 7), ("storage", 9), ("zero_u_feq", 2), ("diag_every", -1), ("reserved", 1),
+    ("collision", 7), ("storage", 9), ("zero_u_feq", 2), ("diag_every", -1), ("tau_clamp", 2),
     ("kappa", float("nan")), ("rho_ref", 0.0),
 ])
 def test_init_rejects_bad_params_before_any_device_work(field, value):

@@ -135,3 +135,53 @@ def test_fp32_storage_short_run_close_to_oracle():
     assert np.abs(phi - ophi)[fluid].max() < 2e-5
     assert np.abs(rho - orho)[fluid].max() < 2e-5
     lat.close()
+
+
+def test_capillary_fp32_against_oracle():
+    """The capillary layout (walls on part of the lattice, 60 degree wetting),
+    FP32 storage against the FP64 oracle: fill length and phi after 3000 steps."""
+    p, inp = wl.c3_capillary(256, 32, 10, analysis.theory_dphi(60.0, 0.04, 0.04), seed=3)
+    say("case capillary 256x32 f32 vs oracle")
+    lat = lbm.lb_init(lbm.make_params(p, "f32"), inp["solid"], inp["phi0"], dphi=inp["dphi"],
+                      rho0=inp["rho0"])
+    orc = make_oracle(p, inp)
+    lbm.lb_step(lat, 3000)
+    orc.step(3000)
+    phi = lbm.lb_read_fields(lat)[0]
+    ophi = orc.fields()[0]
+    fluid = inp["solid"] == 0
+    l_gpu = lbm.lb_fill_length(lat, 128, 224, 30.0)
+    l_orc = (0.5 * (1 + ophi[:, 128:224]))[fluid[:, 128:224]].sum() / 30.0
+    dphi = np.abs(phi - ophi)[fluid].max()
+    say(f"  max|dphi| {dphi:.2e}  fill length {l_gpu:.5f} vs {l_orc:.5f}")
+    assert dphi < 1e-3
+    assert abs(l_gpu - l_orc) < 1e-3 * max(l_orc, 1.0)
+    lat.close()
+
+
+def test_ensemble_sample_against_oracle():
+    """Members of the 256-drop ensemble (FP32, batched) against the FP64 oracle:
+    contact angle within 0.5 degrees and max |d phi| <= 1e-3 after 3000 steps."""
+    descs = [d for d in wl.c5_instances() if d["nx"] == 64][:3]
+    say(f"case ensemble sample {len(descs)} members")
+    members, params, orcs = [], [], []
+    for d in descs:
+        p, inp = wl.c5_member(d, analysis.theory_dphi(d["theta"], 0.04, 0.04))
+        members.append(inp)
+        params.append(lbm.make_params(p, "f32"))
+        orcs.append((p, inp, make_oracle(p, inp)))
+    b = lbm.lb_batch_init(params, members)
+    lbm.lb_batch_step(b, 3000)
+    for k, (d, (p, inp, orc)) in enumerate(zip(descs, orcs)):
+        orc.step(3000)
+        ophi = orc.fields()[0]
+        phi = lbm.lb_batch_read_fields(b, k)[0]
+        fluid = inp["solid"] == 0
+        dphi = np.abs(phi - ophi)[fluid].max()
+        win = (0.0, 64.0, 3.5, 28.0)
+        th = lbm.lb_batch_contact_angle(b, k, *win, 0.5, 1)
+        oca = analysis.contact_angle(ophi, inp["solid"], 0.5, 1, *win)
+        say(f"  member {k}: theta {th:.3f} oracle {oca['theta']:.3f} max|dphi| {dphi:.2e}")
+        assert abs(th - oca["theta"]) < 0.5
+        assert dphi < 1e-3
+    b.close()

@@ -221,6 +221,13 @@ def test_tau_interpolation():
     assert oracle.tau(P, 1.0) == pytest.approx(3.0)
     assert oracle.tau(P, -1.0) == pytest.approx(0.7)
     assert oracle.tau(P, 0.0) == pytest.approx(1.85)
+    # the law is linear in phi beyond the bulk values too (no clamp)
+    assert oracle.tau(P, 1.1) == pytest.approx(3.0 + 0.05 * 2.3)
+    assert oracle.tau(P, -1.1) == pytest.approx(0.7 - 0.05 * 2.3)
+    Q = oracle.make_params(4, 4, tau_alpha=3.0, tau_beta=0.7, tau_clamp=1)
+    assert oracle.tau(Q, 1.1) == pytest.approx(3.0)
+    assert oracle.tau(Q, -1.1) == pytest.approx(0.7)
+    assert oracle.tau(Q, 0.5) == pytest.approx(oracle.tau(P, 0.5))
     assert (3.0 - 0.5) / (0.7 - 0.5) == pytest.approx(12.5)  # R_nu printed in Sec. IV
 
 
