@@ -14,7 +14,11 @@ and contact angle within 0.5 degrees after 10^4 steps).
 Prints one JSON line. `roofline` reports the dominant kernel (the sweep):
 algorithmic bytes (36 populations read and written per lattice update) over the
 average launch duration measured with HIP events on the stream the kernels run
-on. `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+on. `traffic` is the HBM rate from the committed rocprofv3 counter summary
+(profiles/sweep_traffic_4096x2048.json: FETCH_SIZE + WRITE_SIZE per launch,
+calibrated on a copy of known size) over the same launch duration, reported
+only while the kernel sources hash as they did when the counters were taken.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on the host cores.
 """
 import argparse
@@ -28,8 +32,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "MLUPS + HBM GB/s at stated angle/\u03c6 error: FP32/BF16 & batched vs FP64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096x2048.json")
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 80, "bf16s": 80}
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
 ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
@@ -62,6 +68,21 @@ def make_lattice(lbm, p, inp, storage, diag_every=100):
     return lbm.lb_init(lbm.make_params(p, storage, diag_every=diag_every), inp["solid"],
                        inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"],
                        uy0=inp["uy0"])
+
+
+def measured_traffic():
+    """Per-format HBM bytes per sweep launch from the committed counter summary,
+    or None when it is missing or was taken on other kernel sources."""
+    try:
+        from paper_0812_1282_amd import profiling
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("source_sha256") != profiling.source_hash():
+            log("traffic summary was taken on other kernel sources: traffic = null")
+            return None
+        return t["formats"]
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def time_steps(torch, lbm, lat, steps, warmup):
@@ -180,8 +201,17 @@ def main():
     if not args.quick and not args.no_cpu:
         cpu = cpu_baseline(p, inp, args.cpu_steps)
 
+    traffic = measured_traffic()
+
+    def traffic_gbs(st):
+        if not traffic or st not in traffic:
+            return None
+        t = traffic[st]
+        return round((t["fetch_bytes"] + t["write_bytes"]) / (results[st]["ms_per_step"] * 1e-3)
+                     / 1e9, 1)
+
     out = {
-        "metric": "MLUPS",
+        "metric": METRIC,
         "value": round(r["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -200,10 +230,13 @@ def main():
                    "speedup_vs_f64": round(r["mlups"] / results["f64"]["mlups"], 3)
                    if "f64" in results else None},
         "roofline": {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": traffic_gbs(head),
+                     "traffic_ratio": (round(traffic[head]["ratio"], 4)
+                                       if traffic and head in traffic else None)},
         "variants": {s: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                          "gbs": round(v["gbs"], 1), "frac": round(v["frac"], 4),
                          "bytes_per_lu": BYTES_PER_LU[s], "tiles": v["tiles"],
+                         "traffic_gbs": traffic_gbs(s),
                          **({k: (round(x, 6) if isinstance(x, float) else x)
                              for k, x in accuracy.get(s, {}).items()})}
                      for s, v in results.items()},

@@ -62,12 +62,13 @@ extern "C" {
 /* Storage of the populations in device memory. LB_F64 stores f and g in FP64
  * and computes in FP64. The others compute in FP32 on deviations from the rest
  * state of a bulk phase at rho_ref: LB_F32 stores f_i minus that rest value and
- * g in FP32; LB_F16S / LB_BF16S store the f_1..f_8 deviations and g_1..g_8 in
- * 16 bits (scaled by powers of two) and the f_0 deviation and g_0 in 32 bits.
- * In every shifted format g_0 is kept relative to the nearest of -1, 0, 1 and
- * f_0, g_0 are formed from the rounded others, so that the stored populations
- * of a node conserve rho and phi to FP32 precision of small values.
- * Bytes per node per buffer: 144 (FP64), 72 (FP32), 40 (16-bit). */
+ * g in FP32; LB_F16S / LB_BF16S store the f_2, f_4..f_8 deviations and g_1..g_8
+ * in 16 bits (scaled by powers of two) and the f_0, f_1, f_3 deviations and g_0
+ * in 32 bits. In every shifted format g_0 is kept relative to the nearest of
+ * -1, 0, 1, and the 32-bit populations are formed from the rounded others, so
+ * that the stored populations of a node carry its rho, momentum and phi to
+ * FP32 precision of small values.
+ * Bytes per node per buffer: 144 (FP64), 72 (FP32), 44 (16-bit). */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
@@ -219,7 +220,12 @@ int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs)
  * initial fields) advanced together, one fused launch per timestep over the
  * tiles of all members, replayed from a HIP graph. Every member must share
  * storage, collision and the Step 2 flags; arrays are per member as in
- * lb_init. lb_batch_step enqueues nsteps for every member.
+ * lb_init. lb_batch_step enqueues nsteps for every member. With tuning NULL,
+ * lb_batch_init picks the tile shape with lb_batch_autotune (4 timed steps per
+ * candidate); lb_batch_autotune times the candidate shapes over the whole
+ * ensemble with the state restored afterwards and keeps the fastest. The tile
+ * order is fixed: each member's tiles row-major, members in order, dealt to
+ * the XCDs in contiguous ranges. The choice never changes results.
  */
 int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
                   const double* const* wall_dphi, const double* const* phi0,
@@ -233,6 +239,7 @@ int lb_batch_read_populations(lb_batch* b, int32_t member, double* f, double* g)
 int lb_batch_contact_angle(lb_batch* b, int32_t member, double x_lo, double x_hi,
                            double y_lo, double y_hi, double y_wall, int32_t wall_dir,
                            double* theta_deg);
+int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen);
 int lb_batch_get_tuning(lb_batch* b, lb_tuning* t);
 int lb_batch_free(lb_batch* b);
 

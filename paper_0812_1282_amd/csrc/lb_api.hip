@@ -41,6 +41,7 @@ int fail(int code, const std::string& msg) {
 constexpr int kEX[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
 constexpr int kEY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
 constexpr int kGraphSteps = 32;  // timesteps per captured graph (even: parity returns)
+constexpr int kBatchTuneSteps = 4;  // timed steps per candidate when lb_batch_init tunes
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -59,8 +60,8 @@ Layout make_layout(int nx, int ny, int storage) {
     } else if (storage == ST_F32) {
         L.row_bytes = 18 * pitch * 4;
     } else {
-        // f_1..f_8, g_1..g_8 in 16 bits, then f_0 and g_0 in 32 bits
-        L.g0_offset = 16 * pitch * 2 + pitch * 4;
+        // f_2, f_4..f_8, g_1..g_8 in 16 bits, then f_1, f_3, f_0, g_0 in 32 bits
+        L.g0_offset = 14 * pitch * 2 + 3 * pitch * 4;
         L.row_bytes = L.g0_offset + pitch * 4;
     }
     L.buf_bytes = round_up(L.row_bytes * ny, 256);
@@ -1098,6 +1099,9 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
     if (!rc && hipMemcpy(g.d_views, views.data(), n * sizeof(View), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(LB_EHIP, "copy of member views failed");
     if (!rc) rc = build_tiles(g);
+    // No tuning given: time the candidate tile shapes on the ensemble itself
+    // (state restored afterwards, so results do not depend on the choice).
+    if (!rc && !tuning) rc = autotune(g, kBatchTuneSteps, nullptr);
     if (rc) {
         const std::string msg = g_err;
         free_group(g);
@@ -1139,6 +1143,11 @@ int lb_batch_contact_angle(lb_batch* b, int32_t k, double x_lo, double x_hi, dou
     if (rc) return rc;
     return contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
                          nullptr, nullptr, nullptr);
+}
+
+int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen) {
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    return autotune(b->g, steps_per_trial, chosen);
 }
 
 int lb_batch_get_tuning(lb_batch* b, lb_tuning* t) {

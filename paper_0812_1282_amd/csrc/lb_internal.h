@@ -13,8 +13,9 @@ namespace lbm {
 //                   is one block of row_bytes holding, one after another, the
 //                   pitch-long rows (pitch = nx rounded up to 64) of the 18
 //                   planes f_0..f_8, g_0..g_8. In the 16-bit formats the planes
-//                   f_1..f_8, g_1..g_8 are 16-bit (in that order), followed by
-//                   32-bit rows of f_0 and g_0 (g_0 at byte g0_offset). Every
+//                   f_2, f_4..f_8, g_1..g_8 are 16-bit (in that order), followed
+//                   by 32-bit rows of f_1, f_3, f_0 and g_0 (g_0 at byte
+//                   g0_offset). Every
 //                   format except FP64 stores f_i - r_i, r_i the rest state at
 //                   rho_ref in a bulk phase, and g_0 split as b + q (G0Code in
 //                   the kernels).
@@ -44,7 +45,7 @@ struct View {
     int64_t plane;            // nodes per plane including row padding (pitch * ny)
     int64_t row_bytes;        // bytes of one row block of a population buffer
     int64_t g0_offset;        // byte offset of the 32-bit g_0 row inside a block (16-bit;
-                              // the 32-bit f_0 row precedes it)
+                              // the 32-bit f_1, f_3, f_0 rows precede it)
     char* buf[2];
     const uint8_t* nbr;
     const uint8_t* grec;

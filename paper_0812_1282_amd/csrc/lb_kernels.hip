@@ -54,9 +54,11 @@ __device__ inline uint16_t float_to_bf16(float f) {  // round to nearest even
 //   E<p>    element type of plane p
 //   dec/enc conversion between a stored element and the working value
 // Working values of f planes are deviations f_i - r_i in the shifted formats.
-// The 16-bit formats keep the f_1..f_8 deviations times 2^6 and g_1..g_8 times
-// 2^10, so that the small values stay out of the FP16 subnormal range (powers
-// of two: the scaling itself is exact); the f_0 deviation and g_0 are 32-bit.
+// The 16-bit formats keep the f_2, f_4..f_8 deviations times 2^6 and g_1..g_8
+// times 2^10, so that the small values stay out of the FP16 subnormal range
+// (powers of two: the scaling itself is exact); the f_0, f_1, f_3 deviations
+// and g_0 are 32-bit, so that the stored set of a node can carry its mass and
+// momentum exactly (see the store in the sweep).
 template <int S>
 struct Fmt;
 
@@ -75,10 +77,11 @@ struct G0Code {
     }
     // Keep b while |q| <= 3/4 (no switching back and forth for a node at
     // g_0 ~ +-1/2), else move b to the value nearest b + q.
-    __device__ static void rebase(float& q, float& b) {
-        if (__builtin_fabsf(q) > 0.75f) {
-            const float t = b + q;
-            const float nb = t > 0.5f ? 1.0f : (t < -0.5f ? -1.0f : 0.0f);
+    template <class T>
+    __device__ static void rebase(T& q, T& b) {
+        if (q > (T)0.75 || q < (T)-0.75) {
+            const T t = b + q;
+            const T nb = t > (T)0.5 ? (T)1 : (t < (T)-0.5 ? (T)-1 : (T)0);
             q += b - nb;
             b = nb;
         }
@@ -98,9 +101,12 @@ struct Fmt<ST_F64> {
     __device__ static double enc(real x) { return x; }
 };
 
+#ifndef LB_F32_REAL
+#define LB_F32_REAL float
+#endif
 template <>
 struct Fmt<ST_F32> {
-    using real = float;
+    using real = LB_F32_REAL;
     static constexpr bool shifted = true;
     template <int p> using E = typename std::conditional<p == 9, uint32_t, float>::type;
     template <int p>
@@ -122,16 +128,19 @@ struct Fmt16 {
     using real = float;
     static constexpr bool shifted = true;
     static constexpr float kF = 64.0f, kG = 1024.0f;
+    static constexpr bool wide(int p) { return p == 0 || p == 1 || p == 3; }
     template <int p>
     using E = typename std::conditional<
-        p == 9, uint32_t, typename std::conditional<p == 0, float, uint16_t>::type>::type;
-    // Row block: f_1..f_8, g_1..g_8 (16-bit), then f_0 and g_0 (32-bit).
+        p == 9, uint32_t, typename std::conditional<wide(p), float, uint16_t>::type>::type;
+    // Row block: f_2, f_4..f_8, g_1..g_8 (16-bit), then f_1, f_3, f_0, g_0 (32-bit).
+    static constexpr int slot16(int p) { return p == 2 ? 0 : (p == 4 ? 1 : (p < 9 ? p - 3 : p - 4)); }
     template <int p>
     __device__ static int poff(const View& v) {
-        if constexpr (p == 0) return (int)v.g0_offset - v.pitch * 4;
-        else if constexpr (p < 9) return (p - 1) * v.pitch * 2;
+        if constexpr (p == 1) return (int)v.g0_offset - v.pitch * 12;
+        else if constexpr (p == 3) return (int)v.g0_offset - v.pitch * 8;
+        else if constexpr (p == 0) return (int)v.g0_offset - v.pitch * 4;
         else if constexpr (p == 9) return (int)v.g0_offset;
-        else return (p - 2) * v.pitch * 2;
+        else return slot16(p) * v.pitch * 2;
     }
     __device__ static float h2f(uint16_t h) {
         if constexpr (S == ST_F16S) return (float)__builtin_bit_cast(_Float16, h);
@@ -144,14 +153,14 @@ struct Fmt16 {
     template <int p>
     __device__ static real dec(E<p> x) {
         static_assert(p != 9, "g_0 goes through G0Code");
-        if constexpr (p == 0) return x;
+        if constexpr (wide(p)) return x;
         else if constexpr (p < 9) return h2f(x) * (1.0f / kF);
         else return h2f(x) * (1.0f / kG);
     }
     template <int p>
     __device__ static E<p> enc(real x) {
         static_assert(p != 9, "g_0 goes through G0Code");
-        if constexpr (p == 0) return x;
+        if constexpr (wide(p)) return x;
         else if constexpr (p < 9) return f2h(x * kF);
         else return f2h(x * kG);
     }
@@ -182,16 +191,15 @@ __device__ inline Rows rows_of(const char* buf, const View& v, int y, int ym, in
     return Rows{{row_rsrc(buf, v, y), row_rsrc(buf, v, ym), row_rsrc(buf, v, yp)}};
 }
 
-// Per-lane byte offsets: columns x, x-1, x+1 of the main element size and
-// column x of a 32-bit plane (f_0 and g_0 in the 16-bit formats; planes of a
-// size other than the main one are read and written at column x only).
+// Per-lane byte offsets: columns x, x-1, x+1 of the main element size (that of
+// f_2; a plane of twice that size uses them doubled) and column x of plane 9.
 struct ColOff {
     uint32_t c[3];
     uint32_t c9;
 };
 template <int S>
 __device__ inline ColOff col_offsets(uint32_t x, uint32_t xm, uint32_t xp) {
-    constexpr uint32_t sz = sizeof(typename Fmt<S>::template E<1>);
+    constexpr uint32_t sz = sizeof(typename Fmt<S>::template E<2>);
     constexpr uint32_t sz9 = sizeof(typename Fmt<S>::template E<9>);
     return ColOff{{x * sz, xm * sz, xp * sz}, x * sz9};
 }
@@ -238,16 +246,16 @@ __device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
 template <int S, int p>
 __device__ inline typename Fmt<S>::real ldp(Rsrc r, const View& v, const ColOff& co, int c) {
     using E = typename Fmt<S>::template E<p>;
-    constexpr bool wide = sizeof(E) != sizeof(typename Fmt<S>::template E<1>);
-    const uint32_t voff = wide ? co.c9 : co.c[c];
+    constexpr uint32_t ratio = sizeof(E) / sizeof(typename Fmt<S>::template E<2>);
+    const uint32_t voff = p == 9 ? co.c9 : co.c[c] * ratio;
     return Fmt<S>::template dec<p>(buf_ld<E>(r, voff, Fmt<S>::template poff<p>(v)));
 }
 
 template <int S, int p>
 __device__ inline void stp(Rsrc r, const View& v, const ColOff& co, typename Fmt<S>::real x) {
     using E = typename Fmt<S>::template E<p>;
-    constexpr bool wide = sizeof(E) != sizeof(typename Fmt<S>::template E<1>);
-    buf_st<E>(Fmt<S>::template enc<p>(x), r, wide ? co.c9 : co.c[0],
+    constexpr uint32_t ratio = sizeof(E) / sizeof(typename Fmt<S>::template E<2>);
+    buf_st<E>(Fmt<S>::template enc<p>(x), r, p == 9 ? co.c9 : co.c[0] * ratio,
               Fmt<S>::template poff<p>(v));
 }
 
@@ -416,7 +424,9 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const real rho_ref = (real)v.rho_ref;
     const GLOBAL uint8_t* nbr = (const GLOBAL uint8_t*)v.nbr;
     const GLOBAL uint8_t* grec = (const GLOBAL uint8_t*)v.grec;
-    const GLOBAL real* dphi = (const GLOBAL real*)v.dphi;
+    // Wall gradients are FP64 for the FP64 format and FP32 otherwise.
+    using DW = typename std::conditional<S == ST_F64, double, float>::type;
+    const GLOBAL DW* dphi = (const GLOBAL DW*)v.dphi;
 
     const ColOff co = col_offsets<S>(x, xm, xp);
     const ColOff hco = col_offsets<S>(hx, hxm, hxp);
@@ -486,7 +496,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                     const uint32_t sxw = EX[k] == 0 ? x : (EX[k] > 0 ? xp : xm);
                     const size_t s = (size_t)sy * v.pitch + sxw;
                     const uint32_t rec = grec[s];
-                    const real dw = dphi[s];
+                    const real dw = (real)dphi[s];
                     const uint32_t axis = rec & 0xFu;
                     const uint32_t bits = axis ? axis : (rec >> 4);
                     real sum = 0;
@@ -513,8 +523,10 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             ((real)4 * (pn[1] - pn[2]) + (pn[5] - pn[7]) + (pn[8] - pn[6])) * (real)(1.0 / 12.0);
         const real gy =
             ((real)4 * (pn[3] - pn[4]) + (pn[5] - pn[8]) + (pn[7] - pn[6])) * (real)(1.0 / 12.0);
-        const real lap = ((real)4 * (pn[1] + pn[2] + pn[3] + pn[4]) +
-                          (pn[5] + pn[6] + pn[7] + pn[8]) - (real)20 * ph) *
+        // Laplacian from differences to the centre (2 sum w_i (phi_i - phi)):
+        // summing the phi ~ +-1 values first would cancel away FP32 digits.
+        const real lap = ((real)4 * (((pn[1] - ph) + (pn[2] - ph)) + ((pn[3] - ph) + (pn[4] - ph))) +
+                          (((pn[5] - ph) + (pn[6] - ph)) + ((pn[7] - ph) + (pn[8] - ph)))) *
                          (real)(1.0 / 6.0);
 
         // Moments, Eq. (moments): sums of the working values (deviations in the
@@ -580,8 +592,24 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             ev_y = t3 * (bq + r15 * ufy * ufy) + (t3 * gyy - (real)(1.0 / 6.0) * gxx);
             ev_p = t12 * (bq + r15 * upm * upm) - gd + (real)0.25 * gxy;
             ev_m = t12 * (bq + r15 * umm * umm) - gd - (real)0.25 * gxy;
-            const real ox = t3 * rho * ufx, oy = t3 * rho * ufy;
-            const real op = t12 * rho * upm, om = t12 * rho * umm;
+            real ox = t3 * rho * ufx, oy = t3 * rho * ufy;
+            real op = t12 * rho * upm, om = t12 * rho * umm;
+            if constexpr (F::shifted) {
+                // The odd parts carry the momentum of f^eq, 2 (ox + op - om) and
+                // 2 (oy + op + om): exactly rho u* (j, or 0 under Step 2), but in
+                // FP32 rho (j / rho) and the weight sum 2/3 + 4/12 round with a
+                // bias of one sign, and momentum, which the collision never
+                // relaxes, would compound it from step to step. Moving the odd
+                // pattern e_i (it carries momentum and no other moment) makes the
+                // momentum of f^eq its target up to unbiased rounding.
+                const real tx = zf ? (real)0 : jx, ty = zf ? (real)0 : jy;
+                const real cx = (tx - (real)2 * ((ox + op) - om)) * (real)(1.0 / 6.0);
+                const real cy = (ty - (real)2 * ((oy + op) + om)) * (real)(1.0 / 6.0);
+                ox += cx;
+                oy += cy;
+                op += cx + cy;
+                om += cy - cx;
+            }
             feq[1] = ev_x + ox; feq[2] = ev_x - ox;
             feq[3] = ev_y + oy; feq[4] = ev_y - oy;
             feq[5] = ev_p + op; feq[6] = ev_p - op;
@@ -619,7 +647,8 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             const real cw = (real)0.25 * ((real)1 - omega);
             const real m7 = (((f[1] + f[2]) - (f[3] + f[4])) - (real)2 * (ev_x - ev_y)) * cw;
             const real m8 = (((f[5] + f[6]) - (f[7] + f[8])) - (real)2 * (ev_p - ev_m)) * cw;
-            // j - j^eq is zero unless Step 2 removed u from f^eq.
+            // j - j^eq is zero unless Step 2 removed u from f^eq (in the shifted
+            // formats f^eq was adjusted above so that this holds as formed).
             const real qx = zf ? jx * (real)(1.0 / 6.0) : (real)0;
             const real qy = zf ? jy * (real)(1.0 / 6.0) : (real)0;
             fo[0] = feq[0];
@@ -634,20 +663,29 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         }
         const Rsrc out = row_rsrc(dst, v, y);
         if constexpr (S == ST_F16S || S == ST_BF16S) {
-            // Mass-preserving encoding: f_1..f_8 are rounded first and f_0 (a
-            // 32-bit deviation) is stored as the node's density deviation minus
-            // their rounded sum, so the stored populations add up to rho to FP32
-            // precision of a small value. (Collision conserves rho: the exact
-            // f'_0 is the same difference taken before rounding.)
+            // Mass- and momentum-preserving encoding: f_2, f_4..f_8 are rounded
+            // to 16 bits first; the 32-bit f_1 and f_3 are then set so that the
+            // stored set carries the post-collision momentum, and the 32-bit f_0
+            // so that it carries the node's mass (collision conserves it). The
+            // exact f'_1, f'_3, f'_0 satisfy the same relations before rounding.
             using F = Fmt<S>;
-            float acc = 0.0f;
-            static_for<8>([&](auto ic) {
-                constexpr int i = decltype(ic)::value + 1;
-                const uint16_t h = F::f2h(fo[i] * F::kF);
-                acc += F::h2f(h);
-                buf_st<uint16_t>(h, out, co.c[0], F::template poff<i>(v));
+            const real tx = (fo[1] - fo[2]) + (fo[5] - fo[6]) + (fo[8] - fo[7]);
+            const real ty = (fo[3] - fo[4]) + (fo[5] - fo[6]) + (fo[7] - fo[8]);
+            float r[9];
+            static_for<9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (i == 2 || i >= 4) {
+                    const uint16_t h = F::f2h(fo[i] * F::kF);
+                    r[i] = F::h2f(h) * (1.0f / F::kF);
+                    buf_st<uint16_t>(h, out, co.c[0], F::template poff<i>(v));
+                }
             });
-            buf_st<float>(srho - acc * (1.0f / F::kF), out, co.c9, F::template poff<0>(v));
+            const float f1 = tx - (((r[5] - r[6]) + (r[8] - r[7])) - r[2]);
+            const float f3 = ty - (((r[5] - r[6]) + (r[7] - r[8])) - r[4]);
+            buf_st<float>(f1, out, co.c9, F::template poff<1>(v));
+            buf_st<float>(f3, out, co.c9, F::template poff<3>(v));
+            const float f0 = srho - (((f1 + r[2]) + (f3 + r[4])) + ((r[5] + r[6]) + (r[7] + r[8])));
+            buf_st<float>(f0, out, co.c9, F::template poff<0>(v));
         } else {
             static_for<9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;

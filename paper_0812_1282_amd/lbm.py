@@ -28,7 +28,7 @@ EXPORTS = [
     "lb_get_tuning", "lb_autotune", "lb_get_step", "lb_free", "lb_last_error",
     "lb_dphi_for_angle", "lb_batch_init", "lb_batch_step", "lb_batch_read_fields",
     "lb_batch_read_populations", "lb_batch_contact_angle", "lb_batch_get_tuning",
-    "lb_batch_free", "lb_bandwidth_probe",
+    "lb_batch_free", "lb_bandwidth_probe", "lb_batch_autotune",
 ]
 
 
@@ -112,6 +112,7 @@ def load_library(path=LIB_PATH):
         "lb_batch_read_populations": [_VP, i32, _D, _D],
         "lb_batch_contact_angle": [_VP, i32, dbl, dbl, dbl, dbl, dbl, i32, _D],
         "lb_batch_get_tuning": [_VP, ctypes.POINTER(lb_tuning)],
+        "lb_batch_autotune": [_VP, ctypes.c_int32, ctypes.POINTER(lb_tuning)],
         "lb_batch_free": [_VP],
         "lb_bandwidth_probe": [ctypes.c_size_t, i32, _VP, _D],
     }
@@ -379,6 +380,12 @@ def lb_batch_contact_angle(b, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir):
     _check(load_library().lb_batch_contact_angle(b._h, int(k), x_lo, x_hi, y_lo, y_hi, y_wall,
                                                  int(wall_dir), ctypes.byref(th)))
     return th.value
+
+
+def lb_batch_autotune(b, steps_per_trial=4):
+    t = lb_tuning()
+    _check(load_library().lb_batch_autotune(b._h, int(steps_per_trial), ctypes.byref(t)))
+    return t.block_x, t.rows_per_block
 
 
 def lb_batch_get_tuning(b):

@@ -1,0 +1,145 @@
+"""Summaries of rocprofv3 runs of bench.py, as short text and JSON for profiles/.
+
+    python -m paper_0812_1282_amd.profiling trace DB --command CMD --out FILE.md
+    python -m paper_0812_1282_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes N \
+        --nodes N --command CMD --out FILE.json
+
+`trace` tabulates a --kernel-trace database: calls, total, average and median
+duration per kernel. `traffic` turns two --pmc databases (FETCH_SIZE, then
+WRITE_SIZE, in KiB per dispatch) into HBM bytes per sweep launch, each counter
+scaled so that the device copy of a known size that the profiled command runs
+first (bench.py --copy-calibration-mib) reads and writes exactly its size. The
+JSON records a hash of the kernel sources, and bench.py reports the traffic
+only while the sources still hash the same.
+
+Reads only the SQLite output of rocprofv3 (tables `kernels`, `pmc_events`).
+"""
+import argparse
+import collections
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ("csrc/lb_kernels.hip", "csrc/lb_internal.h", "csrc/lb_api.hip")
+STORAGE_NAMES = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16s"}
+# Algorithmic bytes per lattice update: every population read once and written once.
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+_SWEEP = re.compile(r"sweep_kernel<\s*(\d+)\s*,\s*(\d+)\s*,\s*(\d+)\s*,\s*(\w+)\s*,\s*(\w+)\s*>")
+
+
+def sweep_key(name):
+    """(storage, collision, block_x, diag, tau_phi_one) of a sweep kernel name, else None."""
+    m = _SWEEP.search(name)
+    if not m:
+        return None
+    return (STORAGE_NAMES.get(int(m.group(1)), m.group(1)), int(m.group(2)), int(m.group(3)),
+            m.group(4) == "true", m.group(5) == "true")
+
+
+def short_name(name):
+    k = sweep_key(name)
+    if k:
+        st, coll, bx, diag, g1 = k
+        return (f"sweep {st} {'MRT' if coll else 'BGK'} block {bx}"
+                f"{' +diag' if diag else ''}{' tau_phi=1' if g1 else ''}")
+    return name.split("(")[0][:60]
+
+
+def kernel_stats(db):
+    c = sqlite3.connect(db).cursor()
+    rows = c.execute("select name, duration from kernels").fetchall()
+    agg = collections.defaultdict(list)
+    for name, d in rows:
+        agg[name].append(float(d))
+    return agg
+
+
+def trace_summary(db, command):
+    agg = kernel_stats(db)
+    lines = ["# rocprofv3 kernel trace", "", f"Command: `{command}`", "",
+             "| kernel | calls | total ms | avg us | median us |", "|---|---|---|---|---|"]
+    for name, ds in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        ds = sorted(ds)
+        lines.append(f"| {short_name(name)} | {len(ds)} | {sum(ds) / 1e6:.3f} | "
+                     f"{sum(ds) / len(ds) / 1e3:.2f} | {ds[len(ds) // 2] / 1e3:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def per_dispatch(db, counter):
+    c = sqlite3.connect(db).cursor()
+    rows = c.execute("select name, counter_value from pmc_events where counter_name = ?",
+                     (counter,)).fetchall()
+    agg = collections.defaultdict(list)
+    for name, val in rows:
+        agg[name].append(float(val))
+    return agg
+
+
+def traffic_summary(fetch_db, write_db, copy_bytes, nodes, command):
+    fetch = per_dispatch(fetch_db, "FETCH_SIZE")
+    write = per_dispatch(write_db, "WRITE_SIZE")
+    copy_f = [v for k, v in fetch.items() if COPY_KERNEL in k]
+    copy_w = [v for k, v in write.items() if COPY_KERNEL in k]
+    if not copy_f or not copy_w:
+        raise SystemExit("no calibration copy kernel in the databases")
+    f_fac = copy_bytes / (max(copy_f[0]) * 1024.0)
+    w_fac = copy_bytes / (max(copy_w[0]) * 1024.0)
+    out = {"command": command, "source_sha256": source_hash(), "nodes": nodes,
+           "copy_bytes": copy_bytes, "fetch_factor": f_fac, "write_factor": w_fac,
+           "formats": {}}
+    for name, vals in fetch.items():
+        k = sweep_key(name)
+        if not k or k[3]:            # plain sweep launches only (no fused diagnostics)
+            continue
+        st = k[0]
+        fv = sorted(vals)[len(vals) // 2] * 1024.0 * f_fac
+        wv_list = sorted(write.get(name, [0.0]))
+        wv = wv_list[len(wv_list) // 2] * 1024.0 * w_fac
+        alg = BYTES_PER_LU[st] * nodes
+        out["formats"][st] = {"kernel": short_name(name), "dispatches": len(vals),
+                              "fetch_bytes": fv, "write_bytes": wv,
+                              "algorithmic_bytes": alg, "ratio": (fv + wv) / alg}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--command", required=True)
+    t.add_argument("--out", required=True)
+    q = sub.add_parser("traffic")
+    q.add_argument("fetch_db")
+    q.add_argument("write_db")
+    q.add_argument("--copy-bytes", type=float, required=True)
+    q.add_argument("--nodes", type=int, required=True)
+    q.add_argument("--command", required=True)
+    q.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        text = trace_summary(a.db, a.command)
+    else:
+        text = json.dumps(traffic_summary(a.fetch_db, a.write_db, a.copy_bytes, a.nodes,
+                                          a.command), indent=1) + "\n"
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,3 +195,40 @@ def test_equilibrium_angle_equal_viscosity(theta):
     phi = o.fields()[0]
     th = an.contact_angle(phi, inp["solid"], 0.5, 1, 0, 100, 3.5, 47)["theta"]
     assert abs(th - theta) < 3.0
+
+
+@pytest.mark.slow
+def test_capillary_filling_follows_washburn_balance():
+    """Sec. VII, Eq. (washburnlaw) extended by the displaced fluid's resistance:
+    [nu_a l + nu_b (L_c - l)] dl/dt = gamma h cos(theta_a) / 6. The capillary
+    layout at 256 x 32 (walls on [128, 224), h = 30, 60 degree wall, reservoirs
+    joined through the periodic seam) with equal viscosities fills at the constant
+    rate gamma h cos(theta_a) / (6 nu L_c), theta_a the measured advancing angle."""
+    nx, ny, x_in, x_out, h = 256, 32, 128, 224, 30.0
+    p, inp = wl.c3_capillary(nx, ny, 1, an.theory_dphi(60.0, KAPPA, A_L), seed=3)
+    o = make_oracle(p, inp)
+    fluid = inp["solid"] == 0
+    t, lens, angles = [], [], []
+    for k in range(32):
+        o.step(500)
+        phi = o.fields()[0]
+        lens.append((0.5 * (1 + phi[:, x_in:x_out]))[fluid[:, x_in:x_out]].sum() / h)
+        t.append(500.0 * (k + 1))
+        row = phi[ny // 2]
+        xm = next((x + row[x] / (row[x] - row[x + 1]) for x in range(x_in - 16, x_out - 1)
+                   if row[x] > 0 >= row[x + 1]), None)
+        th = np.nan
+        if xm is not None and x_in + 10 < xm < x_out - 10:
+            th = an.contact_angle(phi, inp["solid"], 0.5, 1, xm - 24, xm + 12, 3.5,
+                                  ny - 4.5)["theta"]
+        angles.append(th)
+    t, lens, angles = np.array(t), np.array(lens), np.array(angles)
+    lc = x_out - x_in
+    nu = (p["tau_alpha"] - 0.5) / 3.0
+    sel = (lens > 0.15 * lc) & (lens < 0.45 * lc) & np.isfinite(angles)
+    assert sel.sum() >= 6
+    rate = np.polyfit(t[sel], lens[sel], 1)[0]
+    theta_a = float(np.mean(angles[sel]))
+    assert 60.0 < theta_a < 90.0          # advancing angle above the static 60 degrees
+    pred = an.surface_tension(KAPPA, A_L) * h * np.cos(np.radians(theta_a)) / (6 * nu * lc)
+    assert abs(rate / pred - 1.0) < 0.10
