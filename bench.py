@@ -237,7 +237,7 @@ def main():
                          "gbs": round(v["gbs"], 1), "frac": round(v["frac"], 4),
                          "bytes_per_lu": BYTES_PER_LU[s], "tiles": v["tiles"],
                          "traffic_gbs": traffic_gbs(s),
-                         **({k: (round(x, 6) if isinstance(x, float) else x)
+                         **({k: (float(f"{x:.4g}") if isinstance(x, float) else x)
                              for k, x in accuracy.get(s, {}).items()})}
                      for s, v in results.items()},
         "accuracy_gate": {"max_dphi": GATE_DPHI, "dtheta_deg": GATE_DTHETA,
