@@ -3,9 +3,11 @@
     python -m paper_0812_1282_amd.profiling trace DB --command CMD --out FILE.md
     python -m paper_0812_1282_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes N \
         --nodes N --command CMD --out FILE.json
+    python -m paper_0812_1282_amd.profiling counters DB [DB ...] --command CMD --out FILE.md
 
 `trace` tabulates a --kernel-trace database: calls, total, average and median
-duration per kernel. `traffic` turns two --pmc databases (FETCH_SIZE, then
+duration per kernel. `counters` tabulates the median per dispatch of every
+counter in --pmc databases for the plain sweep launches of each format. `traffic` turns two --pmc databases (FETCH_SIZE, then
 WRITE_SIZE, in KiB per dispatch) into HBM bytes per sweep launch, each counter
 scaled so that the device copy of a known size that the profiled command runs
 first (bench.py --copy-calibration-mib) reads and writes exactly its size. The
@@ -116,6 +118,27 @@ def traffic_summary(fetch_db, write_db, copy_bytes, nodes, command):
     return out
 
 
+def counters_summary(dbs, command):
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for db in dbs:
+        c = sqlite3.connect(db).cursor()
+        for name, cn, v in c.execute("select name, counter_name, counter_value from pmc_events"):
+            k = sweep_key(name)
+            if k and not k[3]:
+                vals[k[0]][cn].append(float(v))
+    names = sorted({cn for d in vals.values() for cn in d})
+    lines = ["# rocprofv3 counters of the sweep (median per dispatch)", "",
+             f"Command: `{command}`", "", "| counter | " + " | ".join(vals) + " |",
+             "|---|" + "---|" * len(vals)]
+    for cn in names:
+        row = []
+        for st in vals:
+            xs = sorted(vals[st].get(cn, []))
+            row.append(f"{xs[len(xs) // 2]:.4g}" if xs else "")
+        lines.append(f"| {cn} | " + " | ".join(row) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -130,9 +153,15 @@ def main(argv=None):
     q.add_argument("--nodes", type=int, required=True)
     q.add_argument("--command", required=True)
     q.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--command", required=True)
+    c.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         text = trace_summary(a.db, a.command)
+    elif a.cmd == "counters":
+        text = counters_summary(a.dbs, a.command)
     else:
         text = json.dumps(traffic_summary(a.fetch_db, a.write_db, a.copy_bytes, a.nodes,
                                           a.command), indent=1) + "\n"
