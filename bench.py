@@ -39,7 +39,7 @@ BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
 ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
-DEFAULT_TILES = {"f64": (256, 64), "f32": (256, 32), "f16s": (256, 32), "bf16s": (256, 32)}
+DEFAULT_TILES = {"f64": (256, 64), "f32": (256, 32), "f16s": (128, 32), "bf16s": (128, 32)}
 
 
 def log(msg):

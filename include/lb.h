@@ -63,8 +63,8 @@ extern "C" {
  * and computes in FP64. The others compute in FP32 on deviations from the rest
  * state of a bulk phase at rho_ref: LB_F32 stores f_i minus that rest value and
  * g in FP32; LB_F16S / LB_BF16S store the f_2, f_4..f_8 deviations and g_1..g_8
- * in 16 bits (scaled by powers of two) and the f_0, f_1, f_3 deviations and g_0
- * in 32 bits. In every shifted format g_0 is kept relative to the nearest of
+ * in 16 bits (scaled by powers of two; f_i and g_i of the same direction share
+ * one 32-bit word) and the f_0, f_1, f_3 deviations and g_0 in 32 bits. In every shifted format g_0 is kept relative to the nearest of
  * -1, 0, 1, and the 32-bit populations are formed from the rounded others, so
  * that the stored populations of a node carry its rho, momentum and phi to
  * FP32 precision of small values.

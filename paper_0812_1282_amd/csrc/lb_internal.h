@@ -12,10 +12,10 @@ namespace lbm {
 //   buf[0], buf[1]  population buffers (A/B ping-pong), row-interleaved: row y
 //                   is one block of row_bytes holding, one after another, the
 //                   pitch-long rows (pitch = nx rounded up to 64) of the 18
-//                   planes f_0..f_8, g_0..g_8. In the 16-bit formats the planes
-//                   f_2, f_4..f_8, g_1..g_8 are 16-bit (in that order), followed
-//                   by 32-bit rows of f_1, f_3, f_0 and g_0 (g_0 at byte
-//                   g0_offset). Every
+//                   planes f_0..f_8, g_0..g_8. In the 16-bit formats a block
+//                   holds 32-bit words pairing f_i and g_i for i = 2, 4..8 (f in
+//                   the low half), the 16-bit rows of g_1 and g_3, then 32-bit
+//                   rows of f_1, f_3, f_0 and g_0 (g_0 at byte g0_offset). Every
 //                   format except FP64 stores f_i - r_i, r_i the rest state at
 //                   rho_ref in a bulk phase, and g_0 split as b + q (G0Code in
 //                   the kernels).

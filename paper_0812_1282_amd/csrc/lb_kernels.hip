@@ -92,6 +92,9 @@ template <>
 struct Fmt<ST_F64> {
     using real = double;
     static constexpr bool shifted = false;
+    static constexpr bool packed = false;
+    template <int p>
+    static constexpr uint32_t colmul() { return 1; }
     template <int p> using E = double;
     template <int p>
     __device__ static int poff(const View& v) { return p * v.pitch * 8; }
@@ -108,6 +111,9 @@ template <>
 struct Fmt<ST_F32> {
     using real = LB_F32_REAL;
     static constexpr bool shifted = true;
+    static constexpr bool packed = false;
+    template <int p>
+    static constexpr uint32_t colmul() { return 1; }
     template <int p> using E = typename std::conditional<p == 9, uint32_t, float>::type;
     template <int p>
     __device__ static int poff(const View& v) { return p * v.pitch * 4; }
@@ -128,20 +134,35 @@ struct Fmt16 {
     using real = float;
     static constexpr bool shifted = true;
     static constexpr float kF = 64.0f, kG = 1024.0f;
+    // f_i and g_i for i = 2, 4..8 are pulled from the same node (or bounce back
+    // together), so they share one 32-bit word: f in the low half, g in the
+    // high half. One load or store then moves both.
+    static constexpr bool packed = true;
+    static constexpr bool paired(int i) { return i == 2 || (i >= 4 && i <= 8); }
     static constexpr bool wide(int p) { return p == 0 || p == 1 || p == 3; }
     template <int p>
     using E = typename std::conditional<
         p == 9, uint32_t, typename std::conditional<wide(p), float, uint16_t>::type>::type;
-    // Row block: f_2, f_4..f_8, g_1..g_8 (16-bit), then f_1, f_3, f_0, g_0 (32-bit).
-    static constexpr int slot16(int p) { return p == 2 ? 0 : (p == 4 ? 1 : (p < 9 ? p - 3 : p - 4)); }
+    // Row block (pitch P): the pair words of i = 2, 4, 5, 6, 7, 8 (4P bytes
+    // each), g_1 and g_3 (16-bit, 2P each), then f_1, f_3, f_0 and g_0 (32-bit).
+    static constexpr int pair_slot(int i) { return i == 2 ? 0 : i - 3; }
+    template <int i>
+    __device__ static int pbase(const View& v) { return pair_slot(i) * v.pitch * 4; }
     template <int p>
     __device__ static int poff(const View& v) {
         if constexpr (p == 1) return (int)v.g0_offset - v.pitch * 12;
         else if constexpr (p == 3) return (int)v.g0_offset - v.pitch * 8;
         else if constexpr (p == 0) return (int)v.g0_offset - v.pitch * 4;
+        else if constexpr (p < 9) return pbase<p>(v);            // low half of a pair
         else if constexpr (p == 9) return (int)v.g0_offset;
-        else return slot16(p) * v.pitch * 2;
+        else if constexpr (p == 10) return v.pitch * 24;         // g_1
+        else if constexpr (p == 12) return v.pitch * 26;         // g_3
+        else return pbase<p - 9>(v) + 2;                         // high half of a pair
     }
+    // Multiplier of the 2-byte column offsets: 1 for the 16-bit planes g_1,
+    // g_3, 2 for the 4-byte columns of the pair words and 32-bit planes.
+    template <int p>
+    static constexpr uint32_t colmul() { return (p == 10 || p == 12) ? 1 : 2; }
     __device__ static float h2f(uint16_t h) {
         if constexpr (S == ST_F16S) return (float)__builtin_bit_cast(_Float16, h);
         else return bf16_to_float(h);
@@ -192,7 +213,8 @@ __device__ inline Rows rows_of(const char* buf, const View& v, int y, int ym, in
 }
 
 // Per-lane byte offsets: columns x, x-1, x+1 of the main element size (that of
-// f_2; a plane of twice that size uses them doubled) and column x of plane 9.
+// f_2; planes with wider columns scale them, Fmt::colmul) and column x of
+// plane 9.
 struct ColOff {
     uint32_t c[3];
     uint32_t c9;
@@ -246,16 +268,14 @@ __device__ inline void buf_st(E x, Rsrc r, uint32_t voff, int soff) {
 template <int S, int p>
 __device__ inline typename Fmt<S>::real ldp(Rsrc r, const View& v, const ColOff& co, int c) {
     using E = typename Fmt<S>::template E<p>;
-    constexpr uint32_t ratio = sizeof(E) / sizeof(typename Fmt<S>::template E<2>);
-    const uint32_t voff = p == 9 ? co.c9 : co.c[c] * ratio;
+    const uint32_t voff = p == 9 ? co.c9 : co.c[c] * Fmt<S>::template colmul<p>();
     return Fmt<S>::template dec<p>(buf_ld<E>(r, voff, Fmt<S>::template poff<p>(v)));
 }
 
 template <int S, int p>
 __device__ inline void stp(Rsrc r, const View& v, const ColOff& co, typename Fmt<S>::real x) {
     using E = typename Fmt<S>::template E<p>;
-    constexpr uint32_t ratio = sizeof(E) / sizeof(typename Fmt<S>::template E<2>);
-    buf_st<E>(Fmt<S>::template enc<p>(x), r, p == 9 ? co.c9 : co.c[0] * ratio,
+    buf_st<E>(Fmt<S>::template enc<p>(x), r, p == 9 ? co.c9 : co.c[0] * Fmt<S>::template colmul<p>(),
               Fmt<S>::template poff<p>(v));
 }
 
@@ -298,6 +318,52 @@ __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uin
             constexpr int i = decltype(ic)::value;
             if constexpr (i > 0) {
                 if ((nb >> (i - 1)) & 1u) out[i] = ldp<S, B + OPP[i]>(R.r[0], v, co, 0);
+            }
+        });
+    }
+}
+
+// 16-bit formats: the populations arriving at fluid node (x, y) that the sweep
+// takes together with phi: the paired f_i (i = 2, 4..8) into fo[i], and g into
+// go (go[0] = q of g_0, base its b). f_0, f_1, f_3 are pulled separately.
+template <int S>
+__device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
+                                  float fo[9], float go[9], float& base) {
+    using F = Fmt<S>;
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
+        constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
+        if constexpr (F::paired(i)) {
+            const uint32_t w = buf_ld<uint32_t>(R.r[r], co.c[c] * 2, F::template pbase<i>(v));
+            fo[i] = F::h2f((uint16_t)(w & 0xFFFFu)) * (1.0f / F::kF);
+            go[i] = F::h2f((uint16_t)(w >> 16)) * (1.0f / F::kG);
+        } else if constexpr (i == 0) {
+            const uint32_t u = buf_ld<uint32_t>(R.r[0], co.c9, F::template poff<9>(v));
+            go[0] = G0Code::q(u);
+            base = G0Code::b(u);
+        } else {
+            go[i] = ldp<S, 9 + i>(R.r[r], v, co, c);
+        }
+    });
+    if (nb != 0u) {
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                if ((nb >> (i - 1)) & 1u) {
+                    // the node's own post-collision values in the opposite direction
+                    if constexpr (F::paired(i) && F::paired(OPP[i])) {
+                        const uint32_t w =
+                            buf_ld<uint32_t>(R.r[0], co.c[0] * 2, F::template pbase<OPP[i]>(v));
+                        fo[i] = F::h2f((uint16_t)(w & 0xFFFFu)) * (1.0f / F::kF);
+                        go[i] = F::h2f((uint16_t)(w >> 16)) * (1.0f / F::kG);
+                    } else if constexpr (F::paired(i)) {
+                        fo[i] = ldp<S, OPP[i]>(R.r[0], v, co, 0);
+                        go[i] = ldp<S, 9 + OPP[i]>(R.r[0], v, co, 0);
+                    } else {
+                        go[i] = ldp<S, 9 + OPP[i]>(R.r[0], v, co, 0);
+                    }
+                }
             }
         });
     }
@@ -367,8 +433,11 @@ __device__ inline real recip(real x) {
 #ifndef LB_WAVES_F32
 #define LB_WAVES_F32 4
 #endif
+#ifndef LB_WAVES_16
+#define LB_WAVES_16 LB_WAVES_F32
+#endif
 template <int S>
-constexpr int kWaves = S == ST_F64 ? LB_WAVES_F64 : LB_WAVES_F32;
+constexpr int kWaves = S == ST_F64 ? LB_WAVES_F64 : (S == ST_F32 ? LB_WAVES_F32 : LB_WAVES_16);
 
 // G1: tau_phi == 1 (the paper's choice for g), so g' = g^eq and the pulled g
 // are needed only for phi; they are then not kept in registers.
@@ -433,13 +502,19 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
 
     // phi at the columns of `c` of the row behind R; the nine pulled g are
     // returned in g unless G1.
-    // (small, base): see phi9.
-    auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9], real& small,
-                      real& base) -> real {
+    // (small, base): see phi9. In the 16-bit formats the paired f_i arrive
+    // with the g and are returned in fp.
+    auto phi_of = [&](const Rows& R, uint32_t nb, const ColOff& c, real g[9], real fp[9],
+                      real& small, real& base) -> real {
         small = 0;
         base = 0;
         if (nb == 0xFFu) return (real)0;
-        if constexpr (G1) {
+        if constexpr (F::packed) {
+            pull_pairs<S>(R, v, c, nb, fp, g, base);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) small += g[i];
+            return base + small;
+        } else if constexpr (G1) {
             return phi9<S>(R, v, c, nb, small, base);
         } else {
             pull9<S, 9>(R, v, c, nb, g, &base);
@@ -449,16 +524,16 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         }
     };
     // Fill ring row yy: this thread's column and the halo columns.
-    auto fill_row = [&](int yy, real g[9], uint32_t& nb, real& small,
+    auto fill_row = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
                         real& base) __attribute__((always_inline)) {
         const int y = wrap(yy, ny);
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
         nb = nrow[x];
-        sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, small, base);
+        sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
         if (halo) {
-            real hg[9], hs, hb;
-            sphi[yy & (kNR - 1)][hcol] = phi_of(R, nrow[hx], hco, hg, hs, hb);
+            real hg[9], hf[9], hs, hb;
+            sphi[yy & (kNR - 1)][hcol] = phi_of(R, nrow[hx], hco, hg, hf, hs, hb);
         }
     };
 
@@ -468,14 +543,26 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     // (gnew), then collide row y (gc). The f pulls of row y are issued before
     // the look-ahead g pulls are consumed, so both sets of loads are in flight
     // together and each row waits for memory once.
-    auto step = [&](int y, real gc[9], uint32_t nbc, real phs, real phb, real gnew[9],
-                    uint32_t& nbnew, real& snew, real& bnew) __attribute__((always_inline)) {
+    auto step = [&](int y, real gc[9], real fc[9], uint32_t nbc, real phs, real phb,
+                    real gnew[9], real fnew[9], uint32_t& nbnew, real& snew,
+                    real& bnew) __attribute__((always_inline)) {
         const bool work = active && nbc != 0xFFu;
         const uint32_t nb = nbc;
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         real f[9];
-        if (work) pull9<S, 0>(R, v, co, nb, f);
-        fill_row(y + 2 * d, gnew, nbnew, snew, bnew);
+        if constexpr (F::packed) {
+            // f_2, f_4..f_8 came with the g of this row; pull f_0, f_1, f_3.
+            if (work) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = fc[i];
+                f[0] = ldp<S, 0>(R.r[0], v, co, 0);
+                f[1] = (nb & 1u) ? ldp<S, 2>(R.r[0], v, co, 0) : ldp<S, 1>(R.r[0], v, co, 1);
+                f[3] = (nb & 4u) ? ldp<S, 4>(R.r[0], v, co, 0) : ldp<S, 3>(R.r[1], v, co, 0);
+            }
+        } else {
+            if (work) pull9<S, 0>(R, v, co, nb, f);
+        }
+        fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         __syncthreads();
         if (!work) return;
 
@@ -662,37 +749,56 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             fo[8] = feq[8] - m8 + qx - qy;
         }
         const Rsrc out = row_rsrc(dst, v, y);
-        if constexpr (S == ST_F16S || S == ST_BF16S) {
+        if constexpr (F::packed) {
             // Mass- and momentum-preserving encoding: f_2, f_4..f_8 are rounded
             // to 16 bits first; the 32-bit f_1 and f_3 are then set so that the
             // stored set carries the post-collision momentum, and the 32-bit f_0
             // so that it carries the node's mass (collision conserves it). The
             // exact f'_1, f'_3, f'_0 satisfy the same relations before rounding.
-            using F = Fmt<S>;
+            // g_1..g_8 (Eq. (gevo); g^eq when tau_phi = 1) are rounded, and g_0
+            // is phi minus their stored sum (G0Code).
             const real tx = (fo[1] - fo[2]) + (fo[5] - fo[6]) + (fo[8] - fo[7]);
             const real ty = (fo[3] - fo[4]) + (fo[5] - fo[6]) + (fo[7] - fo[8]);
             float r[9];
+            uint32_t hf[9], hg[9];
+            real sg = 0;
             static_for<9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                if constexpr (i == 2 || i >= 4) {
-                    const uint16_t h = F::f2h(fo[i] * F::kF);
-                    r[i] = F::h2f(h) * (1.0f / F::kF);
-                    buf_st<uint16_t>(h, out, co.c[0], F::template poff<i>(v));
+                if constexpr (F::paired(i)) {
+                    hf[i] = F::f2h(fo[i] * F::kF);
+                    r[i] = F::h2f((uint16_t)hf[i]) * (1.0f / F::kF);
+                }
+                if constexpr (i > 0) {
+                    const real gi = G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]);
+                    hg[i] = F::f2h(gi * F::kG);
+                    sg += F::h2f((uint16_t)hg[i]);
                 }
             });
+            static_for<9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (F::paired(i))
+                    buf_st<uint32_t>(hf[i] | (hg[i] << 16), out, co.c[0] * 2,
+                                     F::template pbase<i>(v));
+            });
+            buf_st<uint16_t>((uint16_t)hg[1], out, co.c[0], F::template poff<10>(v));
+            buf_st<uint16_t>((uint16_t)hg[3], out, co.c[0], F::template poff<12>(v));
             const float f1 = tx - (((r[5] - r[6]) + (r[8] - r[7])) - r[2]);
             const float f3 = ty - (((r[5] - r[6]) + (r[7] - r[8])) - r[4]);
             buf_st<float>(f1, out, co.c9, F::template poff<1>(v));
             buf_st<float>(f3, out, co.c9, F::template poff<3>(v));
             const float f0 = srho - (((f1 + r[2]) + (f3 + r[4])) + ((r[5] + r[6]) + (r[7] + r[8])));
             buf_st<float>(f0, out, co.c9, F::template poff<0>(v));
+            real q = phs - sg * (1.0f / F::kG), b = phb;
+            G0Code::rebase(q, b);
+            buf_st<uint32_t>(G0Code::enc(q, b), out, co.c9, F::template poff<9>(v));
         } else {
             static_for<9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 stp<S, i>(out, v, co, fo[i]);
             });
         }
-        if constexpr (F::shifted) {
+        if constexpr (F::packed) {
+        } else if constexpr (F::shifted) {
             // Eq. (gevo) for g_1..g_8 (with tau_phi = 1 exactly g^eq); g_0 is
             // phi minus their stored sum, formed from the small parts (BGK for g
             // conserves phi, so this is the exact g'_0).
@@ -721,6 +827,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     };
 
     real gA[9], gB[9], gC[9];
+    real fA[9], fB[9], fC[9];     // paired f of the 16-bit formats
     uint32_t nbA, nbB, nbC;
     real sA, sB, sC, bA, bB, bC;  // phi = b + s of this column (see phi9)
     // Odd strips walk downwards, so the two strips on either side of a strip
@@ -730,20 +837,21 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const int nrow = y1 - y0;
     const int ys = (d > 0) ? y0 : y1 - 1;
     {
-        real gt[9], st, bt;
+        real gt[9], ft[9], st, bt;
         uint32_t nbt;
-        fill_row(ys - 2 * d, gt, nbt, st, bt);
-        fill_row(ys - d, gt, nbt, st, bt);
+        fill_row(ys - 2 * d, gt, ft, nbt, st, bt);
+        fill_row(ys - d, gt, ft, nbt, st, bt);
     }
-    fill_row(ys, gA, nbA, sA, bA);
-    fill_row(ys + d, gB, nbB, sB, bB);
-    // Unrolled by three so the three g rows rotate roles without copies.
+    fill_row(ys, gA, fA, nbA, sA, bA);
+    fill_row(ys + d, gB, fB, nbB, sB, bB);
+    // Unrolled by three so the three rows of pulled values rotate roles
+    // without copies.
     for (int k = 0; k < nrow; k += 3) {
-        step(ys + k * d, gA, nbA, sA, bA, gC, nbC, sC, bC);
+        step(ys + k * d, gA, fA, nbA, sA, bA, gC, fC, nbC, sC, bC);
         if (k + 1 >= nrow) break;
-        step(ys + (k + 1) * d, gB, nbB, sB, bB, gA, nbA, sA, bA);
+        step(ys + (k + 1) * d, gB, fB, nbB, sB, bB, gA, fA, nbA, sA, bA);
         if (k + 2 >= nrow) break;
-        step(ys + (k + 2) * d, gC, nbC, sC, bC, gB, nbB, sB, bB);
+        step(ys + (k + 2) * d, gC, fC, nbC, sC, bC, gB, fB, nbB, sB, bB);
     }
 
     if constexpr (DIAG) {
