@@ -13,6 +13,12 @@ c4  4096 x 2048 drop, MRT, 90 degrees: FP32 and 16-bit shifted storage against
     the FP64 run (max |d phi|, angle, sum of rho drift) at 10^4 and 2 x 10^4 steps
 c5  256-member ensemble, FP32 storage against an FP64 run of every member
     (angle error and max |d phi| per member)
+fig2  Sec. IV protocol: 300 x 100 drop, equilibrate at 90 degrees, then ramp
+      d_perp phi quasi-statically up and down; measured angle against Eq. (theory)
+      for tau 1/1 and 3/0.7, BGK and MRT
+fig5  Sec. VII capillary filling (640 x 50 channel between 480 x 200 reservoirs),
+      M = 0.05, 0.1, 0.5, BGK and MRT: l(t), advancing angle against Ca and its
+      limit Ca -> 0
 """
 import argparse
 import json
@@ -320,13 +326,155 @@ def c5(steps=10000, sample=None):
     return out
 
 
+def theory_angle(dphi, kappa=KAPPA, a=A_LANDAU):
+    """Inverse of Eq. (theory) by bisection on lb_dphi_for_angle (increasing in theta)."""
+    lo, hi = 0.0, 180.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if lbm.lb_dphi_for_angle(mid, kappa, -a, a) < dphi:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def fig2(ramp_steps=1_000_000, equil=30_000, n_updates=1000, every=10_000):
+    """Sec. IV: after equilibrating at d_perp phi = 0, d_perp phi is moved in
+    n_updates equal increments over ramp_steps steps, up to +0.98 of the
+    attainable maximum (non-wetting) or down to -0.98 of it (wetting); the angle is
+    measured every `every` steps and compared with Eq. (theory) at the current
+    d_perp phi. FP64."""
+    _torch()
+    dmax = 0.98 * lbm.lb_dphi_for_angle(180.0, KAPPA, -A_LANDAU, A_LANDAU)
+    out = {"workload": "Fig. 2 protocol, 300x100, R=35, Gamma=0.5", "ramp_steps": ramp_steps,
+           "equil": equil, "runs": []}
+    for ta, tb in ((1.0, 1.0), (3.0, 0.7)):
+        for coll in ("bgk", "mrt"):
+            for sign in (1, -1):
+                p, inp = wl.fig2_drop(ta, tb, coll)
+                lat = _lattice(p, inp)
+                lbm.lb_set_tuning(lat, 64, 8)
+                lbm.lb_step(lat, equil)
+                chunk = ramp_steps // n_updates
+                rec, dead = [], None
+                for k in range(n_updates):
+                    dp = sign * dmax * (k + 1) / n_updates
+                    lbm.lb_set_wall_dphi(lat, np.where(inp["solid"] != 0, dp, 0.0))
+                    lbm.lb_step(lat, chunk)
+                    if ((k + 1) * chunk) % every == 0:
+                        try:
+                            th = lbm.lb_contact_angle(lat, 0.0, 300.0, 3.5, 95.5, 0.5, 1)["theta"]
+                        except lbm.LbError as e:
+                            if lbm.lb_diagnostics(lat, check=False)["rc"] != 0:
+                                dead = (k + 1) * chunk
+                                break
+                            th = None
+                        rec.append((dp, th, theory_angle(dp)))
+                lat.close()
+                ok = [(d, t, q) for d, t, q in rec if t is not None and 30.0 <= q <= 150.0]
+                dev = max((abs(t - q) for d, t, q in ok), default=None)
+                out["runs"].append({"tau": [ta, tb], "collision": coll, "direction": sign,
+                                    "records": rec, "nonfinite_at": dead,
+                                    "max_dev_30_150": dev})
+                print(f"fig2 tau {ta}/{tb} {coll} dir {sign}: max |theta - theory| over "
+                      f"30-150 deg = {dev}", flush=True)
+    return out
+
+
+def fig5(steps=1_000_000, every=5_000, storage="f64", mobilities=(0.05, 0.1, 0.5),
+         collisions=("bgk", "mrt")):
+    """Sec. VII: the three mobilities advance together (one batch per collision
+    operator). Every `every` steps: the column length l (sum of (1 + phi)/2 over
+    the channel divided by h), the meniscus position on the centreline and the
+    advancing angle at the bottom channel wall. v = dl/dt, Ca = v nu_alpha /
+    gamma; cos(theta_a) is fitted linearly in Ca over the records with the
+    meniscus well inside the channel, and theta_a at Ca -> 0 reported."""
+    torch = _torch()
+    a = 0.02
+    gamma = math.sqrt(8 * a * a / 9)
+    dphi = lbm.lb_dphi_for_angle(60.0, a, -a, a)
+    out = {"workload": "Fig. 5 capillary 1600x200 (640x50 channel)", "steps": steps,
+           "storage": storage, "gamma": gamma, "runs": []}
+    for coll in collisions:
+        members, params, geos = [], [], []
+        for m in mobilities:
+            p, inp = wl.fig5_capillary(m, coll, dphi)
+            members.append(inp)
+            params.append(lbm.make_params(p, storage))
+            geos.append(inp["geometry"])
+        nu_a = (params[0].tau_alpha - 0.5) / 3.0
+        b = lbm.lb_batch_init(params, members)
+        rec = [[] for _ in mobilities]
+        done, t_run = 0, 0.0
+        alive = [True] * len(mobilities)
+        while done < steps:
+            t_run += _timed(torch, lambda: lbm.lb_batch_step(b, every))
+            done += every
+            for k, g in enumerate(geos):
+                if not alive[k]:
+                    continue
+                phi = lbm.lb_batch_read_fields(b, k)[0]
+                if not np.all(np.isfinite(phi)):
+                    alive[k] = False
+                    rec[k].append((done, None, None, None))
+                    continue
+                sol = members[k]["solid"]
+                ch = slice(g["x_in"], g["x_out"])
+                l = (0.5 * (1 + phi[:, ch]))[sol[:, ch] == 0].sum() / g["h"]
+                xm = _meniscus_x(phi, g["x_in"] - 40, g["x_out"], (g["y_lo"] + g["y_hi"]) // 2)
+                th = None
+                if xm is not None and g["x_in"] + 40 < xm < g["x_out"] - 40:
+                    try:
+                        th = lbm.lb_batch_contact_angle(b, k, xm - 30.0, xm + 30.0,
+                                                        g["y_lo"] + 3.0, g["y_hi"] - 4.0,
+                                                        g["y_lo"] - 0.5, 1)
+                    except lbm.LbError:
+                        th = None
+                rec[k].append((done, float(l), xm, th))
+            if done % (20 * every) == 0:
+                print(f"fig5 {coll} step {done}: l = "
+                      f"{[round(r[-1][1], 1) if r and r[-1][1] else None for r in rec]}", flush=True)
+        b.close()
+        torch.cuda.empty_cache()
+        for k, m in enumerate(mobilities):
+            r = [x for x in rec[k] if x[1] is not None]
+            t = np.array([x[0] for x in r], float)
+            l = np.array([x[1] for x in r])
+            th = np.array([np.nan if x[3] is None else x[3] for x in r])
+            fit = None
+            if len(l) > 4:
+                v = np.gradient(l, t)
+                ca = v * nu_a / gamma
+                sel = np.isfinite(th) & (ca > 0) & (t >= 0.1 * steps)
+                if sel.sum() >= 5:
+                    slope, c0 = np.polyfit(ca[sel], np.cos(np.radians(th[sel])), 1)
+                    w_sel = sel & (l > 50)
+                    wash = None
+                    if w_sel.sum() >= 5:
+                        ws = np.polyfit(t[w_sel], l[w_sel] ** 2, 1)[0]
+                        pred = (gamma * geos[k]["h"] * np.cos(np.radians(np.nanmean(th[w_sel])))
+                                / (3 * nu_a))
+                        wash = {"l2_slope": float(ws), "washburn_pred": float(pred),
+                                "ratio": float(ws / pred)}
+                    fit = {"theta_a_ca0": float(np.degrees(np.arccos(np.clip(c0, -1, 1)))),
+                           "dcos_dca": float(slope), "ca_range": [float(ca[sel].min()),
+                                                                   float(ca[sel].max())],
+                           "n": int(sel.sum()), "washburn": wash}
+            out["runs"].append({"collision": coll, "mobility": m, "records": rec[k],
+                                "fit": fit, "alive": alive[k],
+                                "mlups": sum(q.nx * q.ny for q in params) * done / t_run / 1e6})
+            print(f"fig5 {coll} M={m}: {fit}", flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig5"])
     ap.add_argument("--out", default="")
     ap.add_argument("--steps", type=int, default=0)
     args = ap.parse_args(argv)
-    fn = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}[args.which]
+    fn = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "fig2": fig2,
+          "fig5": fig5}[args.which]
     if not args.steps:
         res = fn()
     else:

@@ -188,3 +188,41 @@ def c5_member(desc, dphi_wall):
     would take the unclamped law below 1/2."""
     p = params(desc["nx"], desc["ny"], 1.0, desc["tau_beta"], "mrt", tau_clamp=1)
     return p, drop_on_wall(p, 0.4 * desc["ny"], desc["nx"] / 2.0, 0.0, desc["seed"], dphi_wall)
+
+
+def fig5_capillary(mobility, collision, dphi_wall, seed=6):
+    """The capillary-filling geometry of Sec. VII (Fig. 5): a channel of length
+    640 and width h = 50 between two 480 x 200 reservoirs, joined through the
+    periodic seam so that their pressures are equal. The lattice is 1600 x 200.
+    The channel walls are solid blocks over x in [480, 1120), outside the fluid
+    rows 75..124 (wall planes at y = 74.5 and 124.5). phi = +1 (fluid alpha,
+    nu = 0.83) in the left reservoir, -1 (fluid beta, nu = 0.03) in the channel
+    and the right reservoir. gamma = 0.0188 gives a = kappa = 0.02; the mobility
+    M = Gamma (tau_phi - 1/2) gives Gamma = 2 M at tau_phi = 1."""
+    nx, ny, x_in, x_out, y_lo, y_hi = 1600, 200, 480, 1120, 75, 125
+    p = params(nx, ny, 3 * 0.83 + 0.5, 3 * 0.03 + 0.5, collision,
+               A=-0.02, B=0.02, kappa=0.02, Gamma=2.0 * mobility)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[:y_lo, x_in:x_out] = 1
+    solid[y_hi:, x_in:x_out] = 1
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    # signed distance to the nearer front, positive in the left reservoir
+    # (-0.5, x_in - 0.5): fronts at the channel entrance and at the seam
+    inside = x < x_in
+    d = np.where(inside, np.minimum(x + 0.5, x_in - 0.5 - x),
+                 -np.minimum(x - (x_in - 0.5), nx - 0.5 - x))
+    phi = np.tanh(d / _width(p))
+    fluid = solid == 0
+    phi = np.where(fluid, phi + noise((ny, nx), seed), 0.0)
+    geom = dict(x_in=x_in, x_out=x_out, y_lo=y_lo, y_hi=y_hi, h=float(y_hi - y_lo))
+    return p, dict(solid=solid, dphi=wall_field(solid, dphi_wall), phi0=phi,
+                   rho0=np.where(fluid, 1.0, 0.0), ux0=np.zeros((ny, nx)),
+                   uy0=np.zeros((ny, nx)), geometry=geom)
+
+
+def fig2_drop(tau_alpha, tau_beta, collision, seed=7):
+    """The equilibrium-angle set-up of Sec. IV (Fig. 2): 300 x 100, walls at the
+    bottom and top rows, a semicircle of radius 35 on the bottom wall at 90
+    degrees, a = kappa = 0.04, Gamma = 0.5, tau_phi = 1."""
+    p = params(300, 100, tau_alpha, tau_beta, collision, Gamma=0.5)
+    return p, drop_on_wall(p, 35.0, 150.0, 0.0, seed, 0.0)
