@@ -68,11 +68,22 @@ extern "C" {
  * -1, 0, 1, and the 32-bit populations are formed from the rounded others, so
  * that the stored populations of a node carry its rho, momentum and phi to
  * FP32 precision of small values.
- * Bytes per node per buffer: 144 (FP64), 72 (FP32), 44 (16-bit). */
+ * Bytes per node per buffer: 144 (FP64), 72 (FP32), 44 (16-bit), 104 (LB_F64C),
+ * 52 (LB_F32C). */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
 #define LB_BF16S 3
+/* Compressed g (tau_phi = 1 only, Sec. III.A with tau_phi = 1 makes every
+ * post-collision g an equilibrium): instead of g_0..g_8 a node stores the four
+ * numbers its g^eq is made of (phi, Gamma mu and the velocity of g^eq), and a
+ * receiving node forms g^eq_i of its neighbour from them; f as in LB_F64 /
+ * LB_F32. 13 values per node instead of 18. The dynamics are those of the
+ * uncompressed format; only the g populations of S_0 read back differently (as
+ * g_0 = phi_0, g_i = 0), which does not enter any later step because the first
+ * collision replaces g by g^eq of phi_0. lb_init rejects tau_phi != 1. */
+#define LB_F64C 4
+#define LB_F32C 5
 
 typedef struct lb_handle lb_handle;
 typedef struct lb_batch lb_batch;
@@ -87,7 +98,7 @@ typedef struct {
     double tau_phi;       /* relaxation time of g, > 1/2 */
     double rho_ref;       /* reference density of the 16-bit shifted storage */
     int32_t collision;    /* LB_BGK or LB_MRT */
-    int32_t storage;      /* LB_F64, LB_F32, LB_F16S, LB_BF16S */
+    int32_t storage;      /* LB_F64, LB_F32, LB_F16S, LB_BF16S, LB_F64C, LB_F32C */
     int32_t zero_u_feq;   /* Step 2 of Sec. VI: u = 0 at boundary nodes in f^eq */
     int32_t zero_u_geq;   /* the same for g^eq */
     int32_t diag_every;   /* enqueue the non-finite check every k steps (0 = never) */

@@ -59,13 +59,17 @@ Layout make_layout(int nx, int ny, int storage) {
         L.row_bytes = 18 * pitch * 8;
     } else if (storage == ST_F32) {
         L.row_bytes = 18 * pitch * 4;
+    } else if (storage == ST_F64C) {
+        L.row_bytes = 13 * pitch * 8;  // f_0..f_8, then phi, Gamma mu, u_x, u_y
+    } else if (storage == ST_F32C) {
+        L.row_bytes = 13 * pitch * 4;
     } else {
         // f_2, f_4..f_8, g_1..g_8 in 16 bits, then f_1, f_3, f_0, g_0 in 32 bits
         L.g0_offset = 14 * pitch * 2 + 3 * pitch * 4;
         L.row_bytes = L.g0_offset + pitch * 4;
     }
     L.buf_bytes = round_up(L.row_bytes * ny, 256);
-    const size_t dsz = storage == ST_F64 ? 8 : 4;
+    const size_t dsz = (storage == ST_F64 || storage == ST_F64C) ? 8 : 4;
     L.off_buf0 = 0;
     L.off_buf1 = L.buf_bytes;
     L.off_nbr = 2 * L.buf_bytes;
@@ -147,8 +151,10 @@ int validate_params(const lb_params* p) {
     if (!(p->rho_ref > 0)) return fail(LB_EINVAL, "rho_ref must be positive");
     if (p->collision != LB_BGK && p->collision != LB_MRT)
         return fail(LB_EINVAL, "collision must be LB_BGK or LB_MRT");
-    if (p->storage < LB_F64 || p->storage > LB_BF16S)
+    if (p->storage < LB_F64 || p->storage > LB_F32C)
         return fail(LB_EINVAL, "unknown storage format");
+    if ((p->storage == LB_F64C || p->storage == LB_F32C) && p->tau_phi != 1.0)
+        return fail(LB_EINVAL, "the compressed-g formats need tau_phi = 1");
     if ((p->zero_u_feq != 0 && p->zero_u_feq != 1) || (p->zero_u_geq != 0 && p->zero_u_geq != 1))
         return fail(LB_EINVAL, "zero_u flags must be 0 or 1");
     if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
@@ -232,7 +238,7 @@ int upload_dphi(Member& mb, const double* dphi, hipStream_t st) {
     for (int64_t h = 0; h < (int64_t)p.nx * p.ny; ++h)
         if (mb.solid[h] && dphi) mb.dphi[h] = dphi[h];
     char* dst = mb.base + L.off_dphi;
-    if (p.storage == LB_F64) {
+    if (p.storage == LB_F64 || p.storage == LB_F64C) {
         std::vector<double> d((size_t)L.plane, 0.0);
         for (int y = 0; y < p.ny; ++y)
             for (int x = 0; x < p.nx; ++x) d[(size_t)y * L.pitch + x] = mb.dphi[(size_t)y * p.nx + x];

@@ -33,7 +33,7 @@ namespace lbm {
 // contact-line crossings between steps (it is rewritten in full by every step).
 // ---------------------------------------------------------------------------
 
-enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3, ST_F64C = 4, ST_F32C = 5 };
 enum Collision { CO_BGK = 0, CO_MRT = 1 };
 
 constexpr int kPitchAlign = 64;     // elements

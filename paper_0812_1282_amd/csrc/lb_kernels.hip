@@ -92,6 +92,7 @@ template <>
 struct Fmt<ST_F64> {
     using real = double;
     static constexpr bool shifted = false;
+    static constexpr bool gstate = false;
     static constexpr bool packed = false;
     template <int p>
     static constexpr uint32_t colmul() { return 1; }
@@ -111,6 +112,7 @@ template <>
 struct Fmt<ST_F32> {
     using real = LB_F32_REAL;
     static constexpr bool shifted = true;
+    static constexpr bool gstate = false;
     static constexpr bool packed = false;
     template <int p>
     static constexpr uint32_t colmul() { return 1; }
@@ -133,6 +135,7 @@ template <int S>
 struct Fmt16 {
     using real = float;
     static constexpr bool shifted = true;
+    static constexpr bool gstate = false;
     static constexpr float kF = 64.0f, kG = 1024.0f;
     // f_i and g_i for i = 2, 4..8 are pulled from the same node (or bounce back
     // together), so they share one 32-bit word: f in the low half, g in the
@@ -190,6 +193,18 @@ template <>
 struct Fmt<ST_F16S> : Fmt16<ST_F16S> {};
 template <>
 struct Fmt<ST_BF16S> : Fmt16<ST_BF16S> {};
+
+// Compressed g (tau_phi = 1): f as in FP64 / FP32; after f_0..f_8 the row block
+// holds four planes with the node's g-state: phi (plane 9; in the FP32 form
+// split as b + q by G0Code), Gamma mu (10) and the velocity of g^eq (11, 12).
+template <>
+struct Fmt<ST_F64C> : Fmt<ST_F64> {
+    static constexpr bool gstate = true;
+};
+template <>
+struct Fmt<ST_F32C> : Fmt<ST_F32> {
+    static constexpr bool gstate = true;
+};
 
 // Addressing. A row block of a population buffer is reached through a buffer
 // resource (base = the block, record count = its size, so the hardware
@@ -419,6 +434,17 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
     return F::shifted ? base + small : small;
 }
 
+// g^eq_i of Appendix A for a node whose g-state is (phi, Gamma mu, u): the
+// one expression that both the node sending g^eq_i and the node receiving it
+// evaluate, so both obtain the same value bit for bit (compressed formats).
+template <int i, class R>
+__device__ inline R geq_dir(R ph, R gm, R ux, R uy) {
+    constexpr double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+    const R eu = (R)EX[i] * ux + (R)EY[i] * uy;
+    const R bq = gm - (R)0.5 * ph * (ux * ux + uy * uy);
+    return (R)w * (bq + (R)1.5 * ph * eu * eu) + (R)w * ph * eu;
+}
+
 template <class real>
 __device__ inline real recip(real x) {
     if constexpr (std::is_same<real, float>::value) return __builtin_amdgcn_rcpf(x);
@@ -437,7 +463,9 @@ __device__ inline real recip(real x) {
 #define LB_WAVES_16 LB_WAVES_F32
 #endif
 template <int S>
-constexpr int kWaves = S == ST_F64 ? LB_WAVES_F64 : (S == ST_F32 ? LB_WAVES_F32 : LB_WAVES_16);
+constexpr int kWaves = (S == ST_F64 || S == ST_F64C)
+                           ? LB_WAVES_F64
+                           : ((S == ST_F32 || S == ST_F32C) ? LB_WAVES_F32 : LB_WAVES_16);
 
 // G1: tau_phi == 1 (the paper's choice for g), so g' = g^eq and the pulled g
 // are needed only for phi; they are then not kept in registers.
@@ -449,6 +477,11 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     using real = typename F::real;
     constexpr int W = BX + 4;
     __shared__ real sphi[kNR][W];
+    // Compressed g: a ring of four g-state rows of the source buffer (phi word,
+    // Gamma mu, u_x, u_y), with three halo columns on each side.
+    using SW = typename std::conditional<S == ST_F64C, double, float>::type;
+    constexpr int kGS = F::gstate ? 4 : 1, kGW = F::gstate ? BX + 6 : 1;
+    __shared__ SW sst[kGS][4][kGW];
 
     int member = 0, tx, ty, tile_id;
     if (tiles) {  // batched members: the table is already in XCD-aware order
@@ -480,9 +513,13 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const uint32_t x = (uint32_t)((x0 + t) % nx);
     const uint32_t xm = x == 0 ? nx - 1 : x - 1;
     const uint32_t xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
-    // Threads 0..3 also compute phi of the halo columns x0-2, x0-1, x0+BX, x0+BX+1.
-    const bool halo = t < 4;
-    const int hcol = t < 2 ? t : BX + t;
+    // Threads 0, BX/4, BX/2, 3BX/4 (one per wavefront when BX = 256) also
+    // compute phi of the halo columns x0-2, x0-1, x0+BX, x0+BX+1, so that no
+    // wavefront carries the extra work alone (all meet at each row's barrier).
+    constexpr int kHS = BX / 4;
+    const bool halo = t % kHS == 0;
+    const int hid = t / kHS;
+    const int hcol = hid < 2 ? hid : BX + hid;
     const uint32_t hx = (uint32_t)(((x0 - 2 + hcol) % nx + nx) % nx);
     const uint32_t hxm = hx == 0 ? nx - 1 : hx - 1;
     const uint32_t hxp = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
@@ -494,7 +531,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const GLOBAL uint8_t* nbr = (const GLOBAL uint8_t*)v.nbr;
     const GLOBAL uint8_t* grec = (const GLOBAL uint8_t*)v.grec;
     // Wall gradients are FP64 for the FP64 format and FP32 otherwise.
-    using DW = typename std::conditional<S == ST_F64, double, float>::type;
+    using DW = typename std::conditional<S == ST_F64 || S == ST_F64C, double, float>::type;
     const GLOBAL DW* dphi = (const GLOBAL DW*)v.dphi;
 
     const ColOff co = col_offsets<S>(x, xm, xp);
@@ -523,9 +560,93 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             return base + small;
         }
     };
+    // Compressed g: load g-state row yy into the ring (this thread's column;
+    // six threads also the halo columns x0-3..x0-1, x0+BX..x0+BX+2).
+    // threads 1 + k BX/8, k = 0..5, load the six halo columns of the g-state
+    constexpr int kSS = BX / 8;
+    const bool shalo = t >= 1 && (t - 1) % kSS == 0 && (t - 1) / kSS < 6;
+    const int sid = (t - 1) / kSS;
+    const int scol = sid < 3 ? sid : BX + sid;
+    const uint32_t sx = (uint32_t)(((x0 - 3 + scol) % nx + nx) % nx);
+    auto load_state_row = [&](int yy) __attribute__((always_inline)) {
+        if constexpr (F::gstate) {
+            const Rsrc rr = row_rsrc(src, v, wrap(yy, ny));
+            auto ld = [&](uint32_t xx, int col) {
+                if constexpr (S == ST_F32C)
+                    sst[yy & 3][0][col] = __builtin_bit_cast(
+                        float, buf_ld<uint32_t>(rr, xx * 4, F::template poff<9>(v)));
+                else
+                    sst[yy & 3][0][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<9>(v));
+                sst[yy & 3][1][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<10>(v));
+                sst[yy & 3][2][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<11>(v));
+                sst[yy & 3][3][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<12>(v));
+            };
+            ld(x, t + 3);
+            if (shalo) ld(sx, scol);
+        }
+    };
+    // g-state at ring slot sl, column col: phi = b + q and the g^eq inputs.
+    auto gstate_at = [&](int sl, int col, real& ph, real& gm, real& gu, real& gv, real& q,
+                         real& b) __attribute__((always_inline)) {
+        if constexpr (S == ST_F32C) {
+            const uint32_t u = __builtin_bit_cast(uint32_t, (float)sst[sl][0][col]);
+            q = G0Code::q(u);
+            b = G0Code::b(u);
+            ph = b + q;
+        } else {
+            q = (real)sst[sl][0][col];
+            b = 0;
+            ph = q;
+        }
+        gm = (real)sst[sl][1][col];
+        gu = (real)sst[sl][2][col];
+        gv = (real)sst[sl][3][col];
+    };
+    // phi of S_{n+1} at row yy, ring column c: Eq. (stream2) with g' = g^eq
+    // (tau_phi = 1) in flux form, phi + sum of g^eq_i arriving (from r - e_i, or
+    // bounced back at r) - sum of g^eq_i leaving; each g^eq_i is evaluated by
+    // geq_dir from the same stored state on both sides, so sum phi is kept.
+    auto phi_gstate = [&](int yy, int c, uint32_t nb, real& small,
+                          real& base) __attribute__((always_inline)) -> real {
+        small = 0;
+        base = 0;
+        if (nb == 0xFFu) return (real)0;
+        real ph0, gm0, gu0, gv0, q0, b0;
+        gstate_at(yy & 3, c, ph0, gm0, gu0, gv0, q0, b0);
+        real out = 0, in = 0;
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                out += geq_dir<i>(ph0, gm0, gu0, gv0);
+                if ((nb >> (i - 1)) & 1u) {
+                    in += geq_dir<OPP[i]>(ph0, gm0, gu0, gv0);
+                } else {
+                    real ph1, gm1, gu1, gv1, q1, b1;
+                    gstate_at((yy - EY[i]) & 3, c - EX[i], ph1, gm1, gu1, gv1, q1, b1);
+                    in += geq_dir<i>(ph1, gm1, gu1, gv1);
+                }
+            }
+        });
+        small = q0 + (in - out);
+        base = b0;
+        return base + small;
+    };
     // Fill ring row yy: this thread's column and the halo columns.
     auto fill_row = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
                         real& base) __attribute__((always_inline)) {
+        if constexpr (F::gstate) {
+            // the g-state two rows further on, then phi of row yy from the
+            // state rows yy - 1, yy, yy + 1 loaded before
+            load_state_row(yy + 2 * d);
+            const GLOBAL uint8_t* nrow = nbr + (size_t)wrap(yy, ny) * v.pitch;
+            nb = nrow[x];
+            sphi[yy & (kNR - 1)][t + 2] = phi_gstate(yy, t + 3, nb, small, base);
+            if (halo) {
+                real hs, hb;
+                sphi[yy & (kNR - 1)][hcol] = phi_gstate(yy, hcol + 1, nrow[hx], hs, hb);
+            }
+            return;
+        }
         const int y = wrap(yy, ny);
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
@@ -797,7 +918,20 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 stp<S, i>(out, v, co, fo[i]);
             });
         }
-        if constexpr (F::packed) {
+        if constexpr (F::gstate) {
+            // g-state of the node for the next step: phi of S_{n+1} (this
+            // row's phi), Gamma mu and the velocity of g^eq (Step 2 flag).
+            if constexpr (S == ST_F32C) {
+                real q = phs, b = phb;
+                G0Code::rebase(q, b);
+                buf_st<uint32_t>(G0Code::enc(q, b), out, co.c9, F::template poff<9>(v));
+            } else {
+                stp<S, 9>(out, v, co, phs);
+            }
+            stp<S, 10>(out, v, co, rG * mu);
+            stp<S, 11>(out, v, co, ugx);
+            stp<S, 12>(out, v, co, ugy);
+        } else if constexpr (F::packed) {
         } else if constexpr (F::shifted) {
             // Eq. (gevo) for g_1..g_8 (with tau_phi = 1 exactly g^eq); g_0 is
             // phi minus their stored sum, formed from the small parts (BGK for g
@@ -836,14 +970,26 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     // gridDim.x workgroups apart and share an XCD when gridDim.x % 8 == 0.
     const int nrow = y1 - y0;
     const int ys = (d > 0) ? y0 : y1 - 1;
+    if constexpr (F::gstate) {
+        // the state rows the first phi row needs; each later fill reads rows
+        // written by other threads in the fill before it
+        load_state_row(ys - 3 * d);
+        load_state_row(ys - 2 * d);
+        load_state_row(ys - d);
+        __syncthreads();
+    }
     {
         real gt[9], ft[9], st, bt;
         uint32_t nbt;
         fill_row(ys - 2 * d, gt, ft, nbt, st, bt);
+        if constexpr (F::gstate) __syncthreads();
         fill_row(ys - d, gt, ft, nbt, st, bt);
+        if constexpr (F::gstate) __syncthreads();
     }
     fill_row(ys, gA, fA, nbA, sA, bA);
+    if constexpr (F::gstate) __syncthreads();
     fill_row(ys + d, gB, fB, nbB, sB, bB);
+    if constexpr (F::gstate) __syncthreads();
     // Unrolled by three so the three rows of pulled values rotate roles
     // without copies.
     for (int k = 0; k < nrow; k += 3) {
@@ -948,7 +1094,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const int32_t* __restrict
 // the non-hot kernels: absolute FP64 values of a node's pulled populations.
 
 __device__ inline double rest_f(const View& v, int i) {
-    if (v.storage == ST_F64) return 0.0;
+    if (v.storage == ST_F64 || v.storage == ST_F64C) return 0.0;
     return i == 0 ? v.rho_ref - 5.0 / 3.0 * v.p0_ref : (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * v.p0_ref;
 }
 
@@ -964,6 +1110,49 @@ __device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, do
     const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
     const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
     pull9<S, 0>(R, v, co, nb, a);
+    if constexpr (Fmt<S>::gstate) {
+        // g of S_n from the stored g-state: g_i = g^eq_i of r - e_i (or of r in
+        // the opposite direction across a solid link), g_0 = phi - sum g^eq_i.
+        using Rl = typename Fmt<S>::real;
+        using E = typename Fmt<S>::template E<10>;
+        auto st = [&](const Rsrc& rr, uint32_t xx, Rl& ph, Rl& gm, Rl& gu, Rl& gv, double& pa) {
+            if constexpr (S == ST_F32C) {
+                const uint32_t u = buf_ld<uint32_t>(rr, xx * 4, Fmt<S>::template poff<9>(v));
+                ph = G0Code::b(u) + G0Code::q(u);
+                pa = (double)G0Code::b(u) + (double)G0Code::q(u);
+            } else {
+                ph = buf_ld<E>(rr, xx * sizeof(E), Fmt<S>::template poff<9>(v));
+                pa = ph;
+            }
+            gm = buf_ld<E>(rr, xx * sizeof(E), Fmt<S>::template poff<10>(v));
+            gu = buf_ld<E>(rr, xx * sizeof(E), Fmt<S>::template poff<11>(v));
+            gv = buf_ld<E>(rr, xx * sizeof(E), Fmt<S>::template poff<12>(v));
+        };
+        Rl ph0, gm0, gu0, gv0;
+        double pa0;
+        st(R.r[0], (uint32_t)x, ph0, gm0, gu0, gv0, pa0);
+        double out = 0;
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                out += (double)geq_dir<i>(ph0, gm0, gu0, gv0);
+                if ((nb >> (i - 1)) & 1u) {
+                    b[i] = geq_dir<OPP[i]>(ph0, gm0, gu0, gv0);
+                } else {
+                    constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
+                    const uint32_t xx = EX[i] > 0 ? xm : (EX[i] < 0 ? xp : (uint32_t)x);
+                    Rl ph1, gm1, gu1, gv1;
+                    double pa1;
+                    st(R.r[r], xx, ph1, gm1, gu1, gv1, pa1);
+                    b[i] = geq_dir<i>(ph1, gm1, gu1, gv1);
+                }
+            }
+        });
+        for (int i = 0; i < 9; ++i) f[i] = (double)a[i] + rest_f(v, i);
+        g[0] = pa0 - out;
+        for (int i = 1; i < 9; ++i) g[i] = (double)b[i];
+        return true;
+    }
     pull9<S, 9>(R, v, co, nb, b, &base);
     for (int i = 0; i < 9; ++i) {
         f[i] = (double)a[i] + rest_f(v, i);
@@ -999,7 +1188,7 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
         const int64_t s = dev_idx(xx, yy);
         if (v.nbr[s] != 0xFFu) return phi0[host_idx(xx, yy)];
         const uint32_t rec = v.grec[s];
-        const double dw = S == ST_F64 ? reinterpret_cast<const double*>(v.dphi)[s]
+        const double dw = (S == ST_F64 || S == ST_F64C) ? reinterpret_cast<const double*>(v.dphi)[s]
                                       : (double)reinterpret_cast<const float*>(v.dphi)[s];
         const uint32_t axis = rec & 0xFu;
         const uint32_t bits = axis ? axis : (rec >> 4);
@@ -1055,7 +1244,26 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
         const int xs = bb ? x : wrap(x - EX[i], nx), ys = bb ? y : wrap(y - EY[i], ny);
         const Rsrc row = row_rsrc(dst, v, ys);
         const ColOff co = col_offsets<S>((uint32_t)xs, (uint32_t)xs, (uint32_t)xs);
-        if constexpr (i == 0) {
+        if constexpr (Fmt<S>::gstate) {
+            // f as in the other formats; the g-state of S_0 is (phi_0, 0, 0, 0),
+            // whose pulled g has the sum phi_0 (all the first collision uses)
+            const int io = bb ? OPP[i] : i;
+            const double fv = feq[i] - rest_f(v, io);
+            if (bb) stp<S, OPP[i]>(row, v, co, (R)fv);
+            else stp<S, i>(row, v, co, (R)fv);
+            if constexpr (i == 0) {
+                if constexpr (S == ST_F32C) {
+                    const double b = ph > 0.5 ? 1.0 : (ph < -0.5 ? -1.0 : 0.0);
+                    buf_st<uint32_t>(G0Code::enc((float)(ph - b), (float)b), row, co.c9,
+                                     Fmt<S>::template poff<9>(v));
+                } else {
+                    stp<S, 9>(row, v, co, (R)ph);
+                }
+                stp<S, 10>(row, v, co, (R)0);
+                stp<S, 11>(row, v, co, (R)0);
+                stp<S, 12>(row, v, co, (R)0);
+            }
+        } else if constexpr (i == 0) {
             stp<S, 0>(row, v, co, (R)(feq[0] - rest_f(v, 0)));
             if constexpr (Fmt<S>::shifted) {
                 const double b = geq[0] > 0.5 ? 1.0 : (geq[0] < -0.5 ? -1.0 : 0.0);
@@ -1243,6 +1451,8 @@ static hipError_t sweep_one(const View* views, const Tile* tiles, int n1d, int g
 template <int S, int C, int BX, bool D>
 static hipError_t sweep_g(bool g1, const View* vw, const Tile* tl, int n1d, int gx, int gy,
                           int rows, int par, double* parts, hipStream_t st) {
+    if constexpr (Fmt<S>::gstate)  // the compressed formats exist only for tau_phi = 1
+        return sweep_one<S, C, BX, D, true>(vw, tl, n1d, gx, gy, rows, par, parts, st);
     return g1 ? sweep_one<S, C, BX, D, true>(vw, tl, n1d, gx, gy, rows, par, parts, st)
               : sweep_one<S, C, BX, D, false>(vw, tl, n1d, gx, gy, rows, par, parts, st);
 }
@@ -1290,6 +1500,12 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
         case ST_BF16S:
             return sweep_c<ST_BF16S>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
                                      grid_x, grid_y, rows, parity, partials, stream);
+        case ST_F64C:
+            return sweep_c<ST_F64C>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                    grid_x, grid_y, rows, parity, partials, stream);
+        case ST_F32C:
+            return sweep_c<ST_F32C>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
+                                    grid_x, grid_y, rows, parity, partials, stream);
         default:
             return hipErrorInvalidValue;
     }
@@ -1311,6 +1527,8 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
         case ST_F32: hipLaunchKernelGGL(KERNEL<ST_F32>, grid, dim3(256), 0, __VA_ARGS__); break; \
         case ST_F16S: hipLaunchKernelGGL(KERNEL<ST_F16S>, grid, dim3(256), 0, __VA_ARGS__); break; \
         case ST_BF16S: hipLaunchKernelGGL(KERNEL<ST_BF16S>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        case ST_F64C: hipLaunchKernelGGL(KERNEL<ST_F64C>, grid, dim3(256), 0, __VA_ARGS__); break; \
+        case ST_F32C: hipLaunchKernelGGL(KERNEL<ST_F32C>, grid, dim3(256), 0, __VA_ARGS__); break; \
         default: return hipErrorInvalidValue;                                               \
     }
 

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODATA, LB_EIO = 0, -1, -2, -3, -4, -5, -6
 BGK, MRT = 0, 1
-F64, F32, F16S, BF16S = 0, 1, 2, 3
-STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
+F64, F32, F16S, BF16S, F64C, F32C = 0, 1, 2, 3, 4, 5
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S, "f64c": F64C, "f32c": F32C}
 COLLISION = {"bgk": BGK, "mrt": MRT}
 
 EXPORTS = [

@@ -41,6 +41,23 @@ def test_default_params_and_workspace():
     n16 = lbm.lb_workspace_bytes(p)
     # two population buffers of 18 planes, pitch 128 x 50 rows, dominate
     assert n64 > 2 * 18 * 128 * 50 * 8 > n32 > 2 * 18 * 128 * 50 * 4 > n16
+    # compressed g: 13 planes instead of 18
+    p.storage = lbm.F64C
+    n64c = lbm.lb_workspace_bytes(p)
+    p.storage = lbm.F32C
+    n32c = lbm.lb_workspace_bytes(p)
+    assert n64 > n64c > 2 * 13 * 128 * 50 * 8 and n32 > n32c > 2 * 13 * 128 * 50 * 4
+
+
+@pytest.mark.parametrize("storage", ["F64C", "F32C"])
+def test_compressed_formats_need_tau_phi_one(storage):
+    p = lbm.lb_params()
+    lbm.load_library().lb_default_params(16, 8, ctypes.byref(p))
+    p.storage = getattr(lbm, storage)
+    p.tau_phi = 0.8
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_workspace_bytes(p)
+    assert e.value.code == lbm.LB_EINVAL
 
 
 @pytest.mark.parametrize("field,value", [
