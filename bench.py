@@ -5,7 +5,8 @@ MRT, viscosity ratio 10, 90 degree wall), inputs resident in HBM. A step is one
 timestep of the whole hot path (pull-stream, bounce-back, phi tile and wetting
 ghosts, stencils, equilibria, collision, store) with the FP64 conservation sums
 fused into every 100th sweep. Each storage format (FP64, FP32, FP16 / BF16
-shifted deviations with FP32 arithmetic) is timed; the headline `value` is the
+shifted deviations with FP32 arithmetic, and the compressed-g FP64 / FP32 forms
+that store the g-state instead of g) is timed; the headline `value` is the
 fastest format that meets the accuracy gate against FP64 (max |d phi| <= 1e-3
 and contact angle within 0.5 degrees after 10^4 steps).
 
@@ -35,11 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + HBM GB/s at stated angle/\u03c6 error: FP32/BF16 & batched vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096x2048.json")
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
-ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32"}
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104}
+ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32", "f64c": "f64", "f32c": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
-DEFAULT_TILES = {"f64": (256, 64), "f32": (256, 32), "f16s": (128, 32), "bf16s": (128, 32)}
+DEFAULT_TILES = {"f64": (256, 32), "f32": (256, 32), "f16s": (256, 32), "bf16s": (256, 32),
+                 "f64c": (256, 16), "f32c": (256, 32)}
 
 
 def log(msg):
@@ -52,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--validate-steps", type=int, default=10000)
-    ap.add_argument("--storages", default="f64,f32,f16s,bf16s")
+    ap.add_argument("--storages", default="f64,f32,f16s,bf16s,f64c,f32c")
     ap.add_argument("--quick", action="store_true", help="skip validation, batch and CPU legs")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")

@@ -513,13 +513,10 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     const uint32_t x = (uint32_t)((x0 + t) % nx);
     const uint32_t xm = x == 0 ? nx - 1 : x - 1;
     const uint32_t xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
-    // Threads 0, BX/4, BX/2, 3BX/4 (one per wavefront when BX = 256) also
-    // compute phi of the halo columns x0-2, x0-1, x0+BX, x0+BX+1, so that no
-    // wavefront carries the extra work alone (all meet at each row's barrier).
-    constexpr int kHS = BX / 4;
-    const bool halo = t % kHS == 0;
-    const int hid = t / kHS;
-    const int hcol = hid < 2 ? hid : BX + hid;
+    // Threads 0..3 also compute phi of the halo columns x0-2, x0-1, x0+BX,
+    // x0+BX+1. (Spreading these over the wavefronts measured slower.)
+    const bool halo = t < 4;
+    const int hcol = t < 2 ? t : BX + t;
     const uint32_t hx = (uint32_t)(((x0 - 2 + hcol) % nx + nx) % nx);
     const uint32_t hxm = hx == 0 ? nx - 1 : hx - 1;
     const uint32_t hxp = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
@@ -561,12 +558,10 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         }
     };
     // Compressed g: load g-state row yy into the ring (this thread's column;
-    // six threads also the halo columns x0-3..x0-1, x0+BX..x0+BX+2).
-    // threads 1 + k BX/8, k = 0..5, load the six halo columns of the g-state
-    constexpr int kSS = BX / 8;
-    const bool shalo = t >= 1 && (t - 1) % kSS == 0 && (t - 1) / kSS < 6;
-    const int sid = (t - 1) / kSS;
-    const int scol = sid < 3 ? sid : BX + sid;
+    // threads 0..5 also the halo columns x0-3..x0-1, x0+BX..x0+BX+2).
+    // threads 0..5 load the six halo columns of the g-state
+    const bool shalo = t < 6;
+    const int scol = t < 3 ? t : BX + t;
     const uint32_t sx = (uint32_t)(((x0 - 3 + scol) % nx + nx) % nx);
     auto load_state_row = [&](int yy) __attribute__((always_inline)) {
         if constexpr (F::gstate) {

@@ -26,9 +26,9 @@ import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ("csrc/lb_kernels.hip", "csrc/lb_internal.h", "csrc/lb_api.hip")
-STORAGE_NAMES = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16s"}
+STORAGE_NAMES = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16s", 4: "f64c", 5: "f32c"}
 # Algorithmic bytes per lattice update: every population read once and written once.
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
