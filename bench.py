@@ -66,10 +66,13 @@ def parse():
     return ap.parse_args()
 
 
-def make_lattice(lbm, p, inp, storage, diag_every=100):
-    return lbm.lb_init(lbm.make_params(p, storage, diag_every=diag_every), inp["solid"],
-                       inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"],
-                       uy0=inp["uy0"])
+def make_lattice(lbm, p, inp, storage, diag_every=100, tiles=None):
+    lat = lbm.lb_init(lbm.make_params(p, storage, diag_every=diag_every), inp["solid"],
+                      inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"],
+                      uy0=inp["uy0"])
+    if tiles:
+        lbm.lb_set_tuning(lat, *tiles)
+    return lat
 
 
 def measured_traffic():
@@ -154,7 +157,7 @@ def main():
     accuracy = {}
     if not args.quick and "f64" in storages:
         win = (nx / 2 - 1200, nx / 2 + 1200, 4.0, ny - 4.0)
-        ref = make_lattice(lbm, p, inp, "f64")
+        ref = make_lattice(lbm, p, inp, "f64", tiles=results.get("f64", {}).get("tiles"))
         dr0 = lbm.lb_diagnostics(ref)
         lbm.lb_step(ref, args.validate_steps)
         phi_ref = lbm.lb_read_fields(ref)[0]
@@ -167,7 +170,7 @@ def main():
         for st in storages:
             if st == "f64":
                 continue
-            lat = make_lattice(lbm, p, inp, st)
+            lat = make_lattice(lbm, p, inp, st, tiles=results[st]["tiles"])
             d0 = lbm.lb_diagnostics(lat, check=False)
             lbm.lb_step(lat, args.validate_steps)
             d1 = lbm.lb_diagnostics(lat, check=False)
