@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 K = 10
 MARGIN = 3 * K + 4
 W = 112
+TILES = {"f64": (256, 32), "f64c": (256, 16)}   # the shapes bench.py times
 
 
 def say(msg):
@@ -43,13 +44,14 @@ def _window(inp, x0, y0, nx, ny, close_top=False, close_bottom=False):
     return sub
 
 
-@pytest.mark.parametrize("storage", ["f64"])
+@pytest.mark.parametrize("storage", ["f64", "f64c"])
 def test_full_size_sampled_windows(storage):
     p, inp = wl.c4_drop()
     nx, ny = p["nx"], p["ny"]
     say(f"case full size {nx}x{ny} {storage}, {K} steps, bench tiles")
     lat = lbm.lb_init(lbm.make_params(p, storage), inp["solid"], inp["phi0"], dphi=inp["dphi"],
                       rho0=inp["rho0"])
+    lbm.lb_set_tuning(lat, *TILES[storage])
     bx, rows = lbm.lb_get_tuning(lat)
     say(f"  tiles {bx}x{rows}")
     d0 = lbm.lb_diagnostics(lat)
