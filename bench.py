@@ -36,12 +36,15 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + HBM GB/s at stated angle/\u03c6 error: FP32/BF16 & batched vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096x2048.json")
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104}
-ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32", "f64c": "f64", "f32c": "f32"}
+# "ip": the same format updated in place in one buffer (same algorithmic bytes).
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104,
+                "f64ip": 288, "f32ip": 144}
+ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32", "f64c": "f64", "f32c": "f32",
+         "f64ip": "f64", "f32ip": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
 DEFAULT_TILES = {"f64": (256, 32), "f32": (256, 32), "f16s": (256, 32), "bf16s": (256, 32),
-                 "f64c": (256, 16), "f32c": (256, 32)}
+                 "f64c": (256, 16), "f32c": (256, 32), "f64ip": (256, 64), "f32ip": (256, 32)}
 
 
 def log(msg):
@@ -54,7 +57,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--validate-steps", type=int, default=10000)
-    ap.add_argument("--storages", default="f64,f32,f16s,bf16s,f64c,f32c")
+    ap.add_argument("--storages", default="f64,f32,f16s,bf16s,f64c,f32c,f64ip,f32ip")
     ap.add_argument("--quick", action="store_true", help="skip validation, batch and CPU legs")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -67,7 +70,10 @@ def parse():
 
 
 def make_lattice(lbm, p, inp, storage, diag_every=100, tiles=None):
-    lat = lbm.lb_init(lbm.make_params(p, storage, diag_every=diag_every), inp["solid"],
+    inplace = storage.endswith("ip")
+    params = lbm.make_params(p, storage[:-2] if inplace else storage, diag_every=diag_every,
+                             inplace=int(inplace))
+    lat = lbm.lb_init(params, inp["solid"],
                       inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"],
                       uy0=inp["uy0"])
     if tiles:

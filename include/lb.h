@@ -69,7 +69,7 @@ extern "C" {
  * that the stored populations of a node carry its rho, momentum and phi to
  * FP32 precision of small values.
  * Bytes per node per buffer: 144 (FP64), 72 (FP32), 44 (16-bit), 104 (LB_F64C),
- * 52 (LB_F32C). */
+ * 52 (LB_F32C); two buffers, or one plus 8 bytes with lb_params.inplace. */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
@@ -106,6 +106,15 @@ typedef struct {
                              1: phi is clamped to [-1, 1] first, so tau stays between
                              tau_beta and tau_alpha (keeps tau > 1/2 where phi
                              overshoots a bulk value and that bulk tau is close to 1/2) */
+    int32_t inplace;      /* 0: two population buffers, each step pulls from one into
+                             the other. 1: one buffer updated in place (LB_F64 and
+                             LB_F32, single lattices only): even steps take a node's
+                             populations from its neighbours' slots and return them
+                             there, odd steps read and write the node's own slots, so
+                             every node reads and writes the same slots and no second
+                             buffer is needed; the phi of the nodes along tile borders
+                             is formed by a pre-pass into a plane of 8 bytes per node.
+                             Results are bit-identical to inplace = 0. */
 } lb_params;
 
 typedef struct {
@@ -230,7 +239,7 @@ int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs)
  * Batched ensembles: n independent lattices (own sizes, masks, parameters and
  * initial fields) advanced together, one fused launch per timestep over the
  * tiles of all members, replayed from a HIP graph. Every member must share
- * storage, collision and the Step 2 flags; arrays are per member as in
+ * storage, collision and the Step 2 flags and have inplace = 0; arrays are per member as in
  * lb_init. lb_batch_step enqueues nsteps for every member. With tuning NULL,
  * lb_batch_init picks the tile shape with lb_batch_autotune (4 timed steps per
  * candidate); lb_batch_autotune times the candidate shapes over the whole

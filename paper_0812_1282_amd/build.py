@@ -15,7 +15,7 @@ SOURCES = ["lb_kernels.hip", "lb_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # Code object v5 loads under every ROCm 6/7 runtime, including the one
     # bundled with the PyTorch wheel that shares this process.
     "-mcode-object-version=5",
@@ -26,14 +26,44 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+N_FORMATS = 6  # storage formats: one compilation unit of sweep kernels each
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                             "-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+def units():
+    """(object name, source, extra flags) of every compilation unit."""
+    out = [("lb_api", "lb_api.hip", []), ("lb_kernels", "lb_kernels.hip", [])]
+    out += [(f"lb_sweep{k}", "lb_kernels.hip", [f"-DLB_SWEEP_UNIT={k}"]) for k in range(N_FORMATS)]
+    return out
+
+
+def build(verbose: bool = False, jobs: int = None) -> str:
+    """Compile the units in parallel into objects under a temporary folder,
+    then link liblbm.so."""
+    import concurrent.futures
+    import tempfile
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = jobs or max(1, min(len(units()), os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmp:
+        cmds = []
+        for name, src, extra in units():
+            obj = os.path.join(tmp, name + ".o")
+            cmds.append((obj, [HIPCC] + FLAGS + extra + inc +
+                         ["-c", os.path.join(CSRC, src), "-o", obj]))
+        if verbose:
+            for _, c in cmds:
+                print(" ".join(c), flush=True)
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c[1], capture_output=True, text=True),
+                                  cmds))
+        for (_, c), r in zip(cmds, results):
+            if r.returncode != 0:
+                sys.stderr.write(r.stderr)
+                raise subprocess.CalledProcessError(r.returncode, c)
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + \
+            [o for o, _ in cmds]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -49,7 +49,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 namespace lbm {
 
-Layout make_layout(int nx, int ny, int storage) {
+Layout make_layout(int nx, int ny, int storage, bool inplace) {
     Layout L{};
     L.pitch = (int32_t)round_up((size_t)nx, kPitchAlign);
     L.plane = (int64_t)L.pitch * ny;
@@ -71,8 +71,15 @@ Layout make_layout(int nx, int ny, int storage) {
     L.buf_bytes = round_up(L.row_bytes * ny, 256);
     const size_t dsz = (storage == ST_F64 || storage == ST_F64C) ? 8 : 4;
     L.off_buf0 = 0;
-    L.off_buf1 = L.buf_bytes;
-    L.off_nbr = 2 * L.buf_bytes;
+    if (inplace) {  // one population buffer, then the band plane (8 bytes per node)
+        L.off_buf1 = 0;
+        L.off_band = L.buf_bytes;
+        L.off_nbr = L.off_band + round_up(plane * 8, 256);
+    } else {
+        L.off_buf1 = L.buf_bytes;
+        L.off_band = 0;
+        L.off_nbr = 2 * L.buf_bytes;
+    }
     L.off_grec = L.off_nbr + round_up(plane, 256);
     L.off_dphi = L.off_grec + round_up(plane, 256);
     L.off_misc = L.off_dphi + round_up(plane * dsz, 256);
@@ -159,6 +166,9 @@ int validate_params(const lb_params* p) {
         return fail(LB_EINVAL, "zero_u flags must be 0 or 1");
     if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
     if (p->tau_clamp != 0 && p->tau_clamp != 1) return fail(LB_EINVAL, "tau_clamp must be 0 or 1");
+    if (p->inplace != 0 && p->inplace != 1) return fail(LB_EINVAL, "inplace must be 0 or 1");
+    if (p->inplace && p->storage != LB_F64 && p->storage != LB_F32)
+        return fail(LB_EINVAL, "in-place update is available for LB_F64 and LB_F32");
     // One row block of the populations is addressed through a buffer
     // descriptor with a 32-bit record count.
     if ((int64_t)((p->nx + 63) / 64) * 64 * 18 * 8 >= ((int64_t)1 << 31))
@@ -284,6 +294,8 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
     v.g0_offset = (int64_t)L.g0_offset;
     v.buf[0] = mb.base + L.off_buf0;
     v.buf[1] = mb.base + L.off_buf1;
+    v.band = p->inplace ? mb.base + L.off_band : nullptr;
+    v.inplace = p->inplace;
     v.nbr = reinterpret_cast<const uint8_t*>(mb.base + L.off_nbr);
     v.grec = reinterpret_cast<const uint8_t*>(mb.base + L.off_grec);
     v.dphi = mb.base + L.off_dphi;
@@ -314,6 +326,37 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
         stage[n + h] = rho0 ? rho0[h] : p->rho_ref;
         stage[2 * n + h] = ux0 ? ux0[h] : 0.0;
         stage[3 * n + h] = uy0 ? uy0[h] : 0.0;
+    }
+    if (p->inplace) {
+        // phi0 in the band plane; rho0, ux0, uy0 in each node's own slots of
+        // planes 1..3 (FP64) or, as low and high words, 1..6 (FP32).
+        HIPCHK(hipMemcpyAsync(v.band, stage.data(), n * 8, hipMemcpyHostToDevice, st));
+        std::vector<uint32_t> words;
+        for (int q = 0; q < 3; ++q) {
+            const double* src = stage.data() + (size_t)(q + 1) * n;
+            if (p->storage == LB_F64) {
+                HIPCHK(hipMemcpy2DAsync(v.buf[0] + (size_t)(1 + q) * L.pitch * 8, L.row_bytes, src,
+                                        (size_t)nx * 8, (size_t)nx * 8, (size_t)ny,
+                                        hipMemcpyHostToDevice, st));
+            } else {
+                words.resize(2 * n);
+                for (size_t h = 0; h < n; ++h) {
+                    uint64_t u;
+                    std::memcpy(&u, src + h, 8);
+                    words[h] = (uint32_t)u;
+                    words[n + h] = (uint32_t)(u >> 32);
+                }
+                for (int half = 0; half < 2; ++half)
+                    HIPCHK(hipMemcpy2DAsync(v.buf[0] + (size_t)(1 + 2 * q + half) * L.pitch * 4,
+                                            L.row_bytes, words.data() + half * n, (size_t)nx * 4,
+                                            (size_t)nx * 4, (size_t)ny, hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));  // words is reused
+            }
+        }
+        const double* d_phi0 = reinterpret_cast<const double*>(v.band);
+        HIPCHK(launch_init_state(v, d_phi0, nullptr, nullptr, nullptr, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return LB_OK;
     }
     double* d_stage = reinterpret_cast<double*>(v.buf[1]);
     HIPCHK(hipMemcpyAsync(d_stage, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, st));
@@ -380,9 +423,14 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
         const int gx = (m0.p.nx + g.block_x - 1) / g.block_x;
         const int gy = (m0.p.ny + g.rows - 1) / g.rows;
         double* partials = reinterpret_cast<double*>(m0.base + L.off_partials);
+        if (m0.p.inplace) {
+            hipError_t e = launch_band(m0.p.storage, m0.p.tau_phi == 1.0, m0.d_view, m0.p.nx,
+                                       m0.p.ny, g.block_x, g.rows, parity, st);
+            if (e != hipSuccess) return e;
+        }
         hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
-                                    m0.p.tau_phi == 1.0, m0.d_view, nullptr, 0, gx, gy, g.rows,
-                                    parity, partials, st);
+                                    m0.p.tau_phi == 1.0, m0.p.inplace != 0, m0.d_view, nullptr, 0,
+                                    gx, gy, g.rows, parity, partials, st);
         if (e != hipSuccess || !diag) return e;
         return launch_finalize(nullptr, nullptr, 1, gx * gy, partials,
                                reinterpret_cast<double*>(m0.base + L.off_diag),
@@ -390,7 +438,7 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
     }
     const int nt = current_tiles(g);
     hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
-                                m0.p.tau_phi == 1.0, g.d_views, g.d_tiles, nt, 0, 0, g.rows,
+                                m0.p.tau_phi == 1.0, false, g.d_views, g.d_tiles, nt, 0, 0, g.rows,
                                 parity, g.d_partials, st);
     if (e != hipSuccess || !diag) return e;
     return launch_finalize(g.d_tiles, g.d_first, (int)g.m.size(), 0, g.d_partials, g.d_diag,
@@ -451,23 +499,36 @@ int check_flag(Group& g) {
     return LB_OK;
 }
 
+// Device scratch between steps: the other population buffer, or in place the
+// band plane (at least 8 bytes per node).
+std::pair<char*, size_t> scratch_of(const Group& g, const Member& mb) {
+    if (mb.p.inplace) return {mb.base + mb.L.off_band, round_up((size_t)mb.L.plane * 8, 256)};
+    return {mb.view.buf[g.parity ^ 1], mb.L.buf_bytes};
+}
+
 int read_fields(Group& g, int k, double* phi, double* rho, double* ux, double* uy) {
     Member& mb = g.m[k];
-    const size_t n = (size_t)mb.p.nx * mb.p.ny;
-    double* scratch = reinterpret_cast<double*>(mb.view.buf[g.parity ^ 1]);
-    HIPCHK(launch_moments(mb.view, g.parity, scratch, nullptr, 0, 0, 0, g.stream));
+    const int64_t n = (int64_t)mb.p.nx * mb.p.ny;
+    const auto sc = scratch_of(g, mb);
+    double* scratch = reinterpret_cast<double*>(sc.first);
+    const int64_t chunk = std::min<int64_t>(n, (int64_t)(sc.second / 32));
     double* outs[4] = {phi, rho, ux, uy};
-    for (int q = 0; q < 4; ++q)
-        if (outs[q])
-            HIPCHK(hipMemcpyAsync(outs[q], scratch + q * n, n * 8, hipMemcpyDeviceToHost, g.stream));
-    HIPCHK(hipStreamSynchronize(g.stream));
+    for (int64_t first = 0; first < n; first += chunk) {
+        const int64_t cnt = std::min(chunk, n - first);
+        HIPCHK(launch_moments(mb.view, g.parity, first, cnt, scratch, nullptr, 0, 0, 0, g.stream));
+        for (int q = 0; q < 4; ++q)
+            if (outs[q])
+                HIPCHK(hipMemcpyAsync(outs[q] + first, scratch + q * cnt, cnt * 8,
+                                      hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+    }
     return LB_OK;
 }
 
 int read_populations(Group& g, int k, double* f, double* gg) {
     Member& mb = g.m[k];
     const size_t n = (size_t)mb.p.nx * mb.p.ny;
-    double* scratch = reinterpret_cast<double*>(mb.view.buf[g.parity ^ 1]);
+    double* scratch = reinterpret_cast<double*>(scratch_of(g, mb).first);
     for (int pl = 0; pl < 18; ++pl) {
         double* out = pl < 9 ? f : gg;
         if (!out) continue;
@@ -488,8 +549,8 @@ int reduce_member(Group& g, int k, int32_t x_lo, int32_t x_hi, double out[6]) {
     double* diag = reinterpret_cast<double*>(mb.base + L.off_diag);
     int32_t* flag = reinterpret_cast<int32_t*>(mb.base + L.off_flag);
     const int nrec = (int)(((int64_t)mb.p.nx * mb.p.ny + 255) / 256);
-    HIPCHK(launch_moments(mb.view, g.parity, nullptr, partials, (int)L.n_partials, x_lo, x_hi,
-                          g.stream));
+    HIPCHK(launch_moments(mb.view, g.parity, 0, (int64_t)mb.p.nx * mb.p.ny, nullptr, partials,
+                          (int)L.n_partials, x_lo, x_hi, g.stream));
     // A separate scratch flag keeps the sticky periodic flag untouched.
     HIPCHK(launch_finalize(nullptr, nullptr, 1, nrec, partials, diag, flag + 1, g.stream));
     double rec[kPartials];
@@ -511,8 +572,9 @@ int contact_angle(Group& g, int k, double x_lo, double x_hi, double y_lo, double
     const int nx = mb.p.nx, ny = mb.p.ny;
     const Layout& L = mb.L;
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(mb.base + L.off_counter);
-    void* pts = mb.view.buf[g.parity ^ 1];
-    const int64_t cap = (int64_t)(L.buf_bytes / sizeof(Crossing));
+    const auto sc = scratch_of(g, mb);
+    void* pts = sc.first;
+    const int64_t cap = (int64_t)(sc.second / sizeof(Crossing));
     HIPCHK(launch_fill(counter, 0, 8, g.stream));
     HIPCHK(launch_crossings(mb.view, g.parity, pts, cap, counter, g.stream));
     unsigned long long count = 0;
@@ -593,7 +655,7 @@ int contact_angle(Group& g, int k, double x_lo, double x_hi, double y_lo, double
 int alloc_group_single(Group& g, const lb_params* p, void* ext, size_t ext_bytes) {
     g.m.resize(1);
     Member& mb = g.m[0];
-    mb.L = make_layout(p->nx, p->ny, p->storage);
+    mb.L = make_layout(p->nx, p->ny, p->storage, p->inplace != 0);
     if (ext) {
         if (ext_bytes < mb.L.total) return fail(LB_ENOMEM, "device buffer smaller than lb_workspace_bytes");
         if (reinterpret_cast<uintptr_t>(ext) % 256) return fail(LB_EINVAL, "device buffer must be 256-byte aligned");
@@ -643,6 +705,8 @@ int init_single(const lb_params* p, const uint8_t* solid, const double* dphi, co
         return fail(rc, msg);
     }
     g.m[0].n_fluid = nf;
+    // In place, S_0 is stored in the layout that phase 1 reads.
+    g.parity = p->inplace ? 1 : 0;
     *out = h;
     return LB_OK;
 }
@@ -691,14 +755,14 @@ int set_tuning(Group& g, int bx, int rows) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
 
 int autotune(Group& g, int steps, lb_tuning* chosen) {
     if (steps < 1) return fail(LB_EINVAL, "steps_per_trial must be >= 1");
     int max_ny = 0, total = 0;
     for (auto& mb : g.m) { max_ny = std::max(max_ny, mb.p.ny); total += mb.p.nx * mb.p.ny; }
     const auto key = std::make_tuple(g.m[0].p.nx, max_ny, g.m[0].p.storage, g.m[0].p.collision,
-                                     g.batched ? total : -1);
+                                     g.m[0].p.inplace, g.batched ? total : -1);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -789,7 +853,7 @@ int lb_workspace_bytes(const lb_params* p, size_t* bytes) {
     int rc = validate_params(p);
     if (rc) return rc;
     if (!bytes) return fail(LB_EINVAL, "bytes is NULL");
-    *bytes = make_layout(p->nx, p->ny, p->storage).total;
+    *bytes = make_layout(p->nx, p->ny, p->storage, p->inplace != 0).total;
     return LB_OK;
 }
 
@@ -886,7 +950,8 @@ int lb_save(lb_handle* h, const char* path) {
     CkptHeader hd{};
     std::memcpy(hd.magic, "LBMCKPT1", 8);
     hd.version = 1;
-    hd.parity = 0;
+    // In place, the layout of the state depends on the phase.
+    hd.parity = mb.p.inplace ? g.parity : 0;
     hd.step = g.step;
     hd.params = mb.p;
     hd.buf_bytes = buf.size();
@@ -913,7 +978,8 @@ int lb_load(lb_handle* h, const char* path) {
     std::vector<double> dphi;
     std::vector<char> buf;
     bool ok = std::fread(&hd, sizeof(hd), 1, fp) == 1 && std::memcmp(hd.magic, "LBMCKPT1", 8) == 0 &&
-              hd.version == 1 && hd.n == (uint64_t)mb.p.nx * mb.p.ny && hd.buf_bytes == mb.L.buf_bytes;
+              hd.version == 1 && hd.n == (uint64_t)mb.p.nx * mb.p.ny && hd.buf_bytes == mb.L.buf_bytes &&
+              (hd.parity == 0 || (hd.parity == 1 && mb.p.inplace));
     if (ok) {
         solid.resize(hd.n);
         dphi.resize(hd.n);
@@ -930,7 +996,7 @@ int lb_load(lb_handle* h, const char* path) {
         return fail(LB_EINVAL, "checkpoint parameters or mask differ from the handle");
     HIPCHK(hipStreamSynchronize(g.stream));
     HIPCHK(hipMemcpy(mb.view.buf[0], buf.data(), buf.size(), hipMemcpyHostToDevice));
-    g.parity = 0;
+    g.parity = hd.parity;
     g.step = hd.step;
     return upload_dphi(mb, dphi.data(), g.stream);
 }
@@ -1037,6 +1103,9 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
                                  rho0 ? rho0[k] : nullptr, ux0 ? ux0[k] : nullptr,
                                  uy0 ? uy0[k] : nullptr, &nf[k]);
         if (rc) return fail(rc, "member " + std::to_string(k) + ": " + g_err);
+        if (params[k].inplace)
+            return fail(LB_EINVAL, "member " + std::to_string(k) +
+                                       ": in-place update is for single lattices (lb_init)");
         if (params[k].storage != params[0].storage || params[k].collision != params[0].collision ||
             params[k].zero_u_feq != params[0].zero_u_feq ||
             params[k].zero_u_geq != params[0].zero_u_geq ||
@@ -1064,7 +1133,7 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
     size_t tiles_max = 0;
     std::vector<size_t> offs(n);
     for (int k = 0; k < n; ++k) {
-        g.m[k].L = make_layout(params[k].nx, params[k].ny, params[k].storage);
+        g.m[k].L = make_layout(params[k].nx, params[k].ny, params[k].storage, false);
         offs[k] = total;
         total += round_up(g.m[k].L.total, 256);
         tiles_max += g.m[k].L.n_tiles_max;

@@ -304,35 +304,52 @@ __device__ inline void static_for(F&& f) {
     }
 }
 
+// Read modes of the pulls (M): 0 = two buffers (the post-collision f_i of node
+// r at r in plane i); 1 and 2 = the two phases of the in-place update (layout
+// X: f'_i of r at r in plane OPP(i); layout P: the arriving f_i at r in plane i).
+// Row selector (0: y, 1: y-1, 2: y+1) and column selector of the source of the
+// population of direction i, and the plane it is read from.
+template <int M, int i>
+constexpr int src_row() { return M == 2 ? 0 : (EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0)); }
+template <int M, int i>
+constexpr int src_col() { return M == 2 ? 0 : (EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0)); }
+template <int M, int i>
+constexpr int src_plane() { return M == 1 ? OPP[i] : i; }
+// Plane that holds, at r itself, the value pulled across a solid link i (the
+// node's own post-collision value in the opposite direction).
+template <int M, int i>
+constexpr int bounce_plane() { return M == 1 ? i : OPP[i]; }
+
 // Pull the nine populations of set B (0 = f, 9 = g) arriving at fluid node
 // (x, y): from r - e_i, then, for links whose source is solid (bits of nb),
 // the node's own post-collision value in the opposite direction (mid-link
-// bounce-back). Working values (deviations for shifted f).
+// bounce-back). Working values (deviations for shifted f). In read mode 2 the
+// arriving populations, bounce-back included, are already at r.
 // For g in the shifted formats out[0] is the small part q of g_0 and *base its
 // b (G0Code); otherwise *base is 0.
-template <int S, int B>
+template <int S, int B, int M = 0>
 __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
                              typename Fmt<S>::real out[9],
                              typename Fmt<S>::real* base = nullptr) {
     using F = Fmt<S>;
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
-        constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
+        constexpr int r = src_row<M, i>();
+        constexpr int c = src_col<M, i>();
         if constexpr (B == 9 && i == 0 && F::shifted) {
             const uint32_t u = buf_ld<uint32_t>(R.r[0], co.c9, F::template poff<9>(v));
             out[0] = G0Code::q(u);
             if (base) *base = G0Code::b(u);
         } else {
-            out[i] = ldp<S, B + i>(R.r[r], v, co, c);
+            out[i] = ldp<S, B + src_plane<M, i>()>(R.r[r], v, co, c);
             if (B == 9 && i == 0 && base) *base = 0;
         }
     });
-    if (nb != 0u) {
+    if (M != 2 && nb != 0u) {
         static_for<9>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if constexpr (i > 0) {
-                if ((nb >> (i - 1)) & 1u) out[i] = ldp<S, B + OPP[i]>(R.r[0], v, co, 0);
+                if ((nb >> (i - 1)) & 1u) out[i] = ldp<S, B + bounce_plane<M, i>()>(R.r[0], v, co, 0);
             }
         });
     }
@@ -388,7 +405,7 @@ __device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co
 // In the 16-bit formats the g_1..g_8 scale is applied once to their sum. In the
 // shifted formats phi = base + small, small = q + g_1 + ... + g_8 (G0Code); the
 // FP64 format returns small = phi, base = 0.
-template <int S>
+template <int S, int M = 0>
 __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const ColOff& co,
                                              uint32_t nb, typename Fmt<S>::real& small,
                                              typename Fmt<S>::real& base) {
@@ -397,10 +414,11 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
     real gv[9];
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
-        constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
-        using E = typename F::template E<9 + i>;
-        const E e = buf_ld<E>(R.r[r], i == 0 ? co.c9 : co.c[c], F::template poff<9 + i>(v));
+        constexpr int r = src_row<M, i>();
+        constexpr int c = src_col<M, i>();
+        constexpr int pl = 9 + src_plane<M, i>();
+        using E = typename F::template E<pl>;
+        const E e = buf_ld<E>(R.r[r], i == 0 ? co.c9 : co.c[c], F::template poff<pl>(v));
         if constexpr (i == 0 && F::shifted) {
             gv[0] = G0Code::q(e);
             base = G0Code::b(e);
@@ -410,13 +428,14 @@ __device__ inline typename Fmt<S>::real phi9(const Rows& R, const View& v, const
             gv[i] = (real)e;
         }
     });
-    if (nb != 0u) {
+    if (M != 2 && nb != 0u) {
         static_for<9>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if constexpr (i > 0) {
-                using E = typename F::template E<9 + OPP[i]>;
+                constexpr int pl = 9 + bounce_plane<M, i>();
+                using E = typename F::template E<pl>;
                 if ((nb >> (i - 1)) & 1u) {
-                    const E e = buf_ld<E>(R.r[0], co.c[0], F::template poff<9 + OPP[i]>(v));
+                    const E e = buf_ld<E>(R.r[0], co.c[0], F::template poff<pl>(v));
                     if constexpr (std::is_same<E, uint16_t>::value) gv[i] = Fmt16<S>::h2f(e);
                     else gv[i] = (real)e;
                 }
@@ -469,7 +488,13 @@ constexpr int kWaves = (S == ST_F64 || S == ST_F64C)
 
 // G1: tau_phi == 1 (the paper's choice for g), so g' = g^eq and the pulled g
 // are needed only for phi; they are then not kept in registers.
-template <int S, int COLL, int BX, bool DIAG, bool G1>
+// M: read mode (0: two buffers; 1, 2: the phases of the in-place update). In
+// place, a workgroup forms phi only at the nodes it collides; phi at the other
+// nodes of its stencil rows (the rows beyond the ends of its strip, the halo
+// columns, the wrapped columns of idle lanes) comes from the band plane that
+// the pre-pass of this step wrote, since their slots may already hold the
+// populations of the next step.
+template <int S, int COLL, int BX, bool DIAG, bool G1, int M>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
 void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles, int rows,
                   int grid_x, int parity, double* __restrict__ partials) {
@@ -549,9 +574,9 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             for (int i = 0; i < 9; ++i) small += g[i];
             return base + small;
         } else if constexpr (G1) {
-            return phi9<S>(R, v, c, nb, small, base);
+            return phi9<S, M>(R, v, c, nb, small, base);
         } else {
-            pull9<S, 9>(R, v, c, nb, g, &base);
+            pull9<S, 9, M>(R, v, c, nb, g, &base);
 #pragma unroll
             for (int i = 0; i < 9; ++i) small += g[i];
             return base + small;
@@ -643,9 +668,22 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             return;
         }
         const int y = wrap(yy, ny);
-        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
         nb = nrow[x];
+        if constexpr (M != 0) {
+            const GLOBAL real* brow = (const GLOBAL real*)v.band + (size_t)y * v.pitch;
+            if (active && yy >= y0 && yy < y1) {
+                const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+                sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
+            } else {
+                small = 0;
+                base = 0;
+                sphi[yy & (kNR - 1)][t + 2] = brow[x];
+            }
+            if (halo) sphi[yy & (kNR - 1)][hcol] = brow[hx];
+            return;
+        }
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
         if (halo) {
             real hg[9], hf[9], hs, hb;
@@ -676,7 +714,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 f[3] = (nb & 4u) ? ldp<S, 4>(R.r[0], v, co, 0) : ldp<S, 3>(R.r[1], v, co, 0);
             }
         } else {
-            if (work) pull9<S, 0>(R, v, co, nb, f);
+            if (work) pull9<S, 0, M>(R, v, co, nb, f);
         }
         fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         __syncthreads();
@@ -865,6 +903,34 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             fo[8] = feq[8] - m8 + qx - qy;
         }
         const Rsrc out = row_rsrc(dst, v, y);
+        // Store the encoded post-collision value e of direction i of set B
+        // (0 = f, 9 = g): at r in plane B + i (two buffers); in place, phase 0
+        // sends it to r + e_i in plane B + i, or keeps it at r in plane
+        // B + OPP(i) when r + e_i is solid, and phase 1 keeps it at r in plane
+        // B + OPP(i) (the layouts of the next read).
+        auto put = [&](auto bc, auto ic, auto e) __attribute__((always_inline)) {
+            constexpr int B = decltype(bc)::value, i = decltype(ic)::value;
+            using E = decltype(e);
+            constexpr int pi = B + i, po = B + OPP[i];
+            const uint32_t own = pi == 9 ? co.c9 : co.c[0] * F::template colmul<pi>();
+            if constexpr (M == 0) {
+                buf_st<E>(e, out, own, F::template poff<pi>(v));
+            } else if constexpr (M == 2 || i == 0) {
+                buf_st<E>(e, out, own, F::template poff<po>(v));
+            } else {
+                if ((nb >> (OPP[i] - 1)) & 1u) {
+                    buf_st<E>(e, out, own, F::template poff<po>(v));
+                } else {
+                    constexpr int rr = EY[i] > 0 ? 2 : (EY[i] < 0 ? 1 : 0);
+                    constexpr int cc = EX[i] > 0 ? 2 : (EX[i] < 0 ? 1 : 0);
+                    const int yd = rr == 0 ? y : wrap(y + EY[i], ny);
+                    buf_st<E>(e, row_rsrc(dst, v, yd), co.c[cc] * F::template colmul<pi>(),
+                              F::template poff<pi>(v));
+                }
+            }
+        };
+        using IC0 = std::integral_constant<int, 0>;
+        using IC9 = std::integral_constant<int, 9>;
         if constexpr (F::packed) {
             // Mass- and momentum-preserving encoding: f_2, f_4..f_8 are rounded
             // to 16 bits first; the 32-bit f_1 and f_3 are then set so that the
@@ -910,7 +976,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         } else {
             static_for<9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                stp<S, i>(out, v, co, fo[i]);
+                put(IC0{}, ic, F::template enc<i>(fo[i]));
             });
         }
         if constexpr (F::gstate) {
@@ -939,7 +1005,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 const E e = F::template enc<9 + i>(gi);
                 if constexpr (std::is_same<E, uint16_t>::value) sg += Fmt16<S>::h2f(e);
                 else sg += e;
-                buf_st<E>(e, out, co.c[0], F::template poff<9 + i>(v));
+                put(IC9{}, std::integral_constant<int, i>{}, e);
             });
             if constexpr (std::is_same<typename F::template E<10>, uint16_t>::value)
                 sg *= (real)(1.0 / 1024.0);
@@ -950,7 +1016,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             static_for<9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 // Eq. (gevo); with tau_phi = 1 exactly g^eq.
-                stp<S, 9 + i>(out, v, co, G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]));
+                put(IC9{}, ic, F::template enc<9 + i>(G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i])));
             });
         }
     };
@@ -1039,6 +1105,206 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     }
 }
 
+// In-place pre-pass: phi of S_n at the tile-border nodes, into View::band,
+// with the arithmetic of the sweep's own phi (the same pulls summed in the same
+// order, so the sweep obtains the same bits either way). The nodes are the rows
+// y0, y0+1, y1-2, y1-1 of every strip [y0, y1) of `rows` rows (full width) and
+// the columns x0, x0+1, x1-2, x1-1 of every tile column [x0, x1) of `bx`
+// columns (every row): the rows beyond the ends of a strip and the halo
+// columns of a tile for its neighbours, two deep (the stencil and the ghost
+// values at solid nodes). Solid nodes get 0. Rows or columns counted twice on
+// small lattices are written twice with the same value.
+// Each wavefront takes 64 nodes of one row (waves 0 .. row_waves-1: band row
+// w / xchunks, columns 64 (w % xchunks) + lane; then row (w - row_waves) /
+// cchunks, band columns 64 ((w - row_waves) % cchunks) + lane), so the row, and
+// with it the buffer descriptors, is uniform across the wavefront.
+template <int S, int M, bool G1>
+__global__ __launch_bounds__(256) void band_kernel(const View* __restrict__ views, int bx,
+                                                   int rows, int row_waves, int xchunks,
+                                                   int cchunks, int cols_per_row) {
+    using F = Fmt<S>;
+    using real = typename F::real;
+    const View v = views[0];
+    const int nx = v.nx, ny = v.ny;
+    const int lane = (int)(threadIdx.x & 63);
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    int x, y;
+    if (w < row_waves) {
+        const int j = w / xchunks, ch = w - j * xchunks;
+        const int k = j & 3;
+        const int y0 = (j >> 2) * rows, y1 = min(y0 + rows, ny);
+        y = wrap(k < 2 ? y0 + k : y1 - 4 + k, ny);
+        x = ch * 64 + lane;
+        if (x >= nx) return;
+    } else {
+        const int w2 = w - row_waves;
+        y = w2 / cchunks;
+        if (y >= ny) return;
+        const int j = (w2 - y * cchunks) * 64 + lane;
+        if (j >= cols_per_row) return;
+        const int k = j & 3;
+        const int x0 = (j >> 2) * bx, x1 = min(x0 + bx, nx);
+        x = wrap(k < 2 ? x0 + k : x1 - 4 + k, nx);
+    }
+    const size_t node = (size_t)y * v.pitch + x;
+    const uint32_t nb = v.nbr[node];
+    real ph = 0;
+    if (nb != 0xFFu) {
+        const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const Rows R = rows_of(v.buf[0], v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
+        real small = 0, base = 0;
+        if constexpr (G1) {
+            ph = phi9<S, M>(R, v, co, nb, small, base);
+        } else {
+            real g[9];
+            pull9<S, 9, M>(R, v, co, nb, g, &base);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) small += g[i];
+            ph = base + small;
+        }
+    }
+    reinterpret_cast<real*>(v.band)[node] = ph;
+}
+
+// ------------------------------------------------------------------ sweep launchers
+// The sweep and band kernels of one storage format are instantiated by
+// sweep_fmt<S> / band_fmt<S>; the build compiles this file once per format with
+// LB_SWEEP_UNIT = S (those instantiations only) and once without it (every
+// other kernel), so the formats compile in parallel.
+
+struct SweepArgs {
+    int collision, block_x;
+    bool diag, tau_phi_one, inplace;
+    const View* views;
+    const Tile* tiles;
+    int n1d, gx, gy, rows, parity;
+    double* partials;
+    hipStream_t stream;
+};
+
+template <int S, int C, int BX, bool D, bool G1>
+static hipError_t sweep_one(const SweepArgs& a) {
+    const dim3 grid = a.tiles ? dim3(a.n1d) : dim3(a.gx * a.gy);
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        if (a.inplace) {
+            if (a.parity)
+                hipLaunchKernelGGL((sweep_kernel<S, C, BX, D, G1, 2>), grid, dim3(BX), 0, a.stream,
+                                   a.views, a.tiles, a.rows, a.gx, a.parity, a.partials);
+            else
+                hipLaunchKernelGGL((sweep_kernel<S, C, BX, D, G1, 1>), grid, dim3(BX), 0, a.stream,
+                                   a.views, a.tiles, a.rows, a.gx, a.parity, a.partials);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((sweep_kernel<S, C, BX, D, G1, 0>), grid, dim3(BX), 0, a.stream, a.views,
+                       a.tiles, a.rows, a.gx, a.parity, a.partials);
+    return hipGetLastError();
+}
+
+template <int S, int C, int BX, bool D>
+static hipError_t sweep_g(const SweepArgs& a) {
+    if constexpr (Fmt<S>::gstate)  // the compressed formats exist only for tau_phi = 1
+        return sweep_one<S, C, BX, D, true>(a);
+    return a.tau_phi_one ? sweep_one<S, C, BX, D, true>(a) : sweep_one<S, C, BX, D, false>(a);
+}
+
+template <int S, int C, int BX>
+static hipError_t sweep_d(const SweepArgs& a) {
+    return a.diag ? sweep_g<S, C, BX, true>(a) : sweep_g<S, C, BX, false>(a);
+}
+
+template <int S, int C>
+static hipError_t sweep_b(const SweepArgs& a) {
+    switch (a.block_x) {
+        case 64: return sweep_d<S, C, 64>(a);
+        case 128: return sweep_d<S, C, 128>(a);
+        case 256: return sweep_d<S, C, 256>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+hipError_t sweep_fmt(const SweepArgs& a) {
+    if (a.inplace && (a.tiles || (S != ST_F64 && S != ST_F32))) return hipErrorInvalidValue;
+    return a.collision == CO_MRT ? sweep_b<S, CO_MRT>(a) : sweep_b<S, CO_BGK>(a);
+}
+
+struct BandArgs {
+    int bx, rows, row_waves, xchunks, cchunks, cols_per_row;
+};
+
+template <int S>
+hipError_t band_fmt(bool g1, int parity, dim3 grid, const View* v, BandArgs b, hipStream_t st) {
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, v, b.bx, b.rows, b.row_waves,
+                               b.xchunks, b.cchunks, b.cols_per_row);
+        };
+        if (parity) {
+            if (g1) go(band_kernel<S, 2, true>);
+            else go(band_kernel<S, 2, false>);
+        } else {
+            if (g1) go(band_kernel<S, 1, true>);
+            else go(band_kernel<S, 1, false>);
+        }
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+#ifdef LB_SWEEP_UNIT
+template hipError_t sweep_fmt<LB_SWEEP_UNIT>(const SweepArgs&);
+template hipError_t band_fmt<LB_SWEEP_UNIT>(bool, int, dim3, const View*, BandArgs, hipStream_t);
+#else
+#define LB_EXTERN_FMT(S)                                                                   \
+    extern template hipError_t sweep_fmt<S>(const SweepArgs&);                             \
+    extern template hipError_t band_fmt<S>(bool, int, dim3, const View*, BandArgs, hipStream_t);
+LB_EXTERN_FMT(ST_F64)
+LB_EXTERN_FMT(ST_F32)
+LB_EXTERN_FMT(ST_F16S)
+LB_EXTERN_FMT(ST_BF16S)
+LB_EXTERN_FMT(ST_F64C)
+LB_EXTERN_FMT(ST_F32C)
+#undef LB_EXTERN_FMT
+
+hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool tau_phi_one,
+                        bool inplace, const View* d_views, const Tile* d_tiles, int n_blocks_1d,
+                        int grid_x, int grid_y, int rows, int parity, double* partials,
+                        hipStream_t stream) {
+    const SweepArgs a{collision, block_x, diag, tau_phi_one, inplace, d_views, d_tiles,
+                      n_blocks_1d, grid_x, grid_y, rows, parity, partials, stream};
+    switch (storage) {
+        case ST_F64: return sweep_fmt<ST_F64>(a);
+        case ST_F32: return sweep_fmt<ST_F32>(a);
+        case ST_F16S: return sweep_fmt<ST_F16S>(a);
+        case ST_BF16S: return sweep_fmt<ST_BF16S>(a);
+        case ST_F64C: return sweep_fmt<ST_F64C>(a);
+        case ST_F32C: return sweep_fmt<ST_F32C>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_band(int storage, bool tau_phi_one, const View* d_view, int nx, int ny,
+                       int block_x, int rows, int parity, hipStream_t stream) {
+    if (block_x < 1 || rows < 1) return hipErrorInvalidValue;
+    const int64_t strips = (ny + rows - 1) / rows, tiles_x = (nx + block_x - 1) / block_x;
+    BandArgs b;
+    b.bx = block_x;
+    b.rows = rows;
+    b.xchunks = (nx + 63) / 64;
+    b.cols_per_row = (int)(4 * tiles_x);
+    b.cchunks = (b.cols_per_row + 63) / 64;
+    const int64_t row_waves = 4 * strips * b.xchunks;
+    const int64_t waves = row_waves + (int64_t)ny * b.cchunks;
+    if (waves >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    b.row_waves = (int)row_waves;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (storage == ST_F64) return band_fmt<ST_F64>(tau_phi_one, parity, grid, d_view, b, stream);
+    if (storage == ST_F32) return band_fmt<ST_F32>(tau_phi_one, parity, grid, d_view, b, stream);
+    return hipErrorInvalidValue;
+}
+
 // Sum per-workgroup partial records in a fixed order: one workgroup per member.
 __global__ __launch_bounds__(256) void finalize_kernel(const int32_t* __restrict__ member_first,
                                                        int n_records_single,
@@ -1104,6 +1370,23 @@ __device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, do
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
     const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        if (v.inplace) {
+            if (parity) {
+                pull9<S, 0, 2>(R, v, co, nb, a);
+                pull9<S, 9, 2>(R, v, co, nb, b, &base);
+            } else {
+                pull9<S, 0, 1>(R, v, co, nb, a);
+                pull9<S, 9, 1>(R, v, co, nb, b, &base);
+            }
+            for (int i = 0; i < 9; ++i) {
+                f[i] = (double)a[i] + rest_f(v, i);
+                g[i] = (double)b[i];
+            }
+            g[0] += (double)base;
+            return true;
+        }
+    }
     pull9<S, 0>(R, v, co, nb, a);
     if constexpr (Fmt<S>::gstate) {
         // g of S_n from the stored g-state: g_i = g^eq_i of r - e_i (or of r in
@@ -1176,7 +1459,28 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
     const int nx = v.nx, ny = v.ny, pitch = v.pitch;
     const int64_t r = (int64_t)y * pitch + x;
     const uint32_t nb = v.nbr[r];
-    if (nb == 0xFFu) return;
+    // In place, rho0, ux0, uy0 are staged in the node's own slots of planes
+    // 1..3 (FP64) or 1..6 (FP32, low and high words), which only this thread
+    // reads and then overwrites (layout P keeps every value at its node).
+    constexpr int kEs = sizeof(typename Fmt<S>::template E<2>);
+    const Rsrc own = row_rsrc(v.buf[0], v, y);
+    auto staged = [&](int q) -> double {
+        if constexpr (kEs == 8) {
+            return buf_ld<double>(own, (uint32_t)x * 8, (1 + q) * pitch * 8);
+        } else {
+            const uint64_t lo = buf_ld<uint32_t>(own, (uint32_t)x * 4, (1 + 2 * q) * pitch * 4);
+            const uint64_t hi = buf_ld<uint32_t>(own, (uint32_t)x * 4, (2 + 2 * q) * pitch * 4);
+            return __builtin_bit_cast(double, lo | (hi << 32));
+        }
+    };
+    if (nb == 0xFFu) {
+        if (v.inplace)
+            for (int pl = 1; pl <= (kEs == 8 ? 3 : 6); ++pl) {
+                if constexpr (kEs == 8) buf_st<double>(0.0, own, (uint32_t)x * 8, pl * pitch * 8);
+                else buf_st<uint32_t>(0u, own, (uint32_t)x * 4, pl * pitch * 4);
+            }
+        return;
+    }
     auto host_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * nx + wrap(xx, nx); };
     auto dev_idx = [&](int xx, int yy) { return (int64_t)wrap(yy, ny) * pitch + wrap(xx, nx); };
     auto phi_at = [&](int xx, int yy) -> double {
@@ -1206,7 +1510,10 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
     const double lap = (4.0 * (pn[1] + pn[2] + pn[3] + pn[4]) + (pn[5] + pn[6] + pn[7] + pn[8]) -
                         20.0 * ph) / 6.0;
     const int64_t hi = (int64_t)y * nx + x;
-    const double rho = rho0[hi], ux = ux0[hi], uy = uy0[hi];
+    const bool ip = (S == ST_F64 || S == ST_F32) && v.inplace;
+    const double rho = ip ? staged(0) : rho0[hi];
+    const double ux = ip ? staged(1) : ux0[hi];
+    const double uy = ip ? staged(2) : uy0[hi];
     const double mu = ph * (v.A + v.B * ph * ph) - v.kappa * lap;
     const double p0 = rho / 3.0 + ph * ph * (0.5 * v.A + 0.75 * v.B * ph * ph);
     const double usq = ux * ux + uy * uy;
@@ -1232,6 +1539,30 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
     geq[0] = ph - sg;
     char* dst = v.buf[0];
     using R = typename Fmt<S>::real;
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        if (ip) {
+            // layout P (the populations that have arrived at r, at r in plane
+            // i), which the first step reads in phase 1: S_0 at r is the
+            // equilibrium of r itself
+            const ColOff co = col_offsets<S>((uint32_t)x, (uint32_t)x, (uint32_t)x);
+            static_for<9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                stp<S, i>(own, v, co, (R)(feq[i] - rest_f(v, i)));
+                if constexpr (i == 0) {
+                    if constexpr (Fmt<S>::shifted) {
+                        const double b = geq[0] > 0.5 ? 1.0 : (geq[0] < -0.5 ? -1.0 : 0.0);
+                        buf_st<uint32_t>(G0Code::enc((float)(geq[0] - b), (float)b), own, co.c9,
+                                         Fmt<S>::template poff<9>(v));
+                    } else {
+                        stp<S, 9>(own, v, co, (R)geq[0]);
+                    }
+                } else {
+                    stp<S, 9 + i>(own, v, co, (R)geq[i]);
+                }
+            });
+            return;
+        }
+    }
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const bool bb = i > 0 && ((nb >> (i - 1)) & 1u);
@@ -1279,18 +1610,20 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
 
 // ------------------------------------------------------------------ read-back
 
-// Moments of S_n at every node: optional compact FP64 fields (phi, rho, ux, uy
-// planes of nx*ny) and FP64 partial records of sums over fluid nodes (sum rho,
-// sum phi, kinetic energy, max |u|, count, and sum (1+phi)/2 for x in [x_lo, x_hi)).
+// Moments of S_n at the nodes first .. first+count-1 (host order): optional
+// compact FP64 fields (phi, rho, ux, uy planes of count values) and FP64
+// partial records of sums over fluid nodes (sum rho, sum phi, kinetic energy,
+// max |u|, count, and sum (1+phi)/2 for x in [x_lo, x_hi)).
 template <int S>
-__global__ __launch_bounds__(256) void moments_kernel(View v, int parity,
+__global__ __launch_bounds__(256) void moments_kernel(View v, int parity, int64_t first,
+                                                      int64_t count,
                                                       double* __restrict__ fields,
                                                       double* __restrict__ partials,
                                                       int32_t x_lo, int32_t x_hi) {
-    const int64_t n = (int64_t)v.nx * v.ny;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t id = first + k;
     double a[6] = {0, 0, 0, 0, 0, 0};
-    if (id < n) {
+    if (k < count) {
         const int x = (int)(id % v.nx), y = (int)(id / v.nx);
         double ph = 0, rho = 0, ux = 0, uy = 0;
         double f[9], g[9];
@@ -1313,10 +1646,10 @@ __global__ __launch_bounds__(256) void moments_kernel(View v, int parity,
             if (x >= x_lo && x < x_hi) a[5] = 0.5 * (1.0 + ph);
         }
         if (fields) {
-            fields[id] = ph;
-            fields[n + id] = rho;
-            fields[2 * n + id] = ux;
-            fields[3 * n + id] = uy;
+            fields[k] = ph;
+            fields[count + k] = rho;
+            fields[2 * count + k] = ux;
+            fields[3 * count + k] = uy;
         }
     }
     if (partials) {
@@ -1429,83 +1762,6 @@ __global__ void fill_kernel(uint8_t* __restrict__ p, uint8_t value, size_t bytes
     for (size_t k = i; k < bytes; k += stride) p[k] = value;
 }
 
-// ------------------------------------------------------------------ launchers
-
-// Passed from launch_sweep down the template dispatch (host side, per call).
-static thread_local bool g_tau_phi_one = false;
-
-template <int S, int C, int BX, bool D, bool G1>
-static hipError_t sweep_one(const View* views, const Tile* tiles, int n1d, int gx, int gy,
-                            int rows, int parity, double* partials, hipStream_t st) {
-    const dim3 grid = tiles ? dim3(n1d) : dim3(gx * gy);
-    hipLaunchKernelGGL((sweep_kernel<S, C, BX, D, G1>), grid, dim3(BX), 0, st, views, tiles,
-                       rows, gx, parity, partials);
-    return hipGetLastError();
-}
-
-template <int S, int C, int BX, bool D>
-static hipError_t sweep_g(bool g1, const View* vw, const Tile* tl, int n1d, int gx, int gy,
-                          int rows, int par, double* parts, hipStream_t st) {
-    if constexpr (Fmt<S>::gstate)  // the compressed formats exist only for tau_phi = 1
-        return sweep_one<S, C, BX, D, true>(vw, tl, n1d, gx, gy, rows, par, parts, st);
-    return g1 ? sweep_one<S, C, BX, D, true>(vw, tl, n1d, gx, gy, rows, par, parts, st)
-              : sweep_one<S, C, BX, D, false>(vw, tl, n1d, gx, gy, rows, par, parts, st);
-}
-
-template <int S, int C, int BX>
-static hipError_t sweep_d(bool diag, const View* vw, const Tile* tl, int n1d, int gx, int gy,
-                          int rows, int par, double* parts, hipStream_t st) {
-    const bool g1 = g_tau_phi_one;
-    return diag ? sweep_g<S, C, BX, true>(g1, vw, tl, n1d, gx, gy, rows, par, parts, st)
-                : sweep_g<S, C, BX, false>(g1, vw, tl, n1d, gx, gy, rows, par, parts, st);
-}
-
-template <int S, int C>
-static hipError_t sweep_b(int bx, bool diag, const View* vw, const Tile* tl, int n1d, int gx,
-                          int gy, int rows, int par, double* parts, hipStream_t st) {
-    switch (bx) {
-        case 64: return sweep_d<S, C, 64>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
-        case 128: return sweep_d<S, C, 128>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
-        case 256: return sweep_d<S, C, 256>(diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int S>
-static hipError_t sweep_c(int coll, int bx, bool diag, const View* vw, const Tile* tl, int n1d,
-                          int gx, int gy, int rows, int par, double* parts, hipStream_t st) {
-    return coll == CO_MRT ? sweep_b<S, CO_MRT>(bx, diag, vw, tl, n1d, gx, gy, rows, par, parts, st)
-                          : sweep_b<S, CO_BGK>(bx, diag, vw, tl, n1d, gx, gy, rows, par, parts, st);
-}
-
-hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool tau_phi_one,
-                        const View* d_views, const Tile* d_tiles, int n_blocks_1d, int grid_x,
-                        int grid_y, int rows, int parity, double* partials, hipStream_t stream) {
-    g_tau_phi_one = tau_phi_one;
-    switch (storage) {
-        case ST_F64:
-            return sweep_c<ST_F64>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                   grid_x, grid_y, rows, parity, partials, stream);
-        case ST_F32:
-            return sweep_c<ST_F32>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                   grid_x, grid_y, rows, parity, partials, stream);
-        case ST_F16S:
-            return sweep_c<ST_F16S>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                    grid_x, grid_y, rows, parity, partials, stream);
-        case ST_BF16S:
-            return sweep_c<ST_BF16S>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                     grid_x, grid_y, rows, parity, partials, stream);
-        case ST_F64C:
-            return sweep_c<ST_F64C>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                    grid_x, grid_y, rows, parity, partials, stream);
-        case ST_F32C:
-            return sweep_c<ST_F32C>(collision, block_x, diag, d_views, d_tiles, n_blocks_1d,
-                                    grid_x, grid_y, rows, parity, partials, stream);
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
 hipError_t launch_finalize(const Tile*, const int32_t* member_first, int n_members,
                            int n_records_single, const double* partials, double* diag_out,
                            int32_t* flag, hipStream_t stream) {
@@ -1534,12 +1790,14 @@ hipError_t launch_init_state(const View& v, const double* phi0, const double* rh
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const View& v, int parity, double* fields, double* partials,
-                          int n_records, int32_t x_lo, int32_t x_hi, hipStream_t stream) {
-    const dim3 grid(blocks_for((int64_t)v.nx * v.ny));
+hipError_t launch_moments(const View& v, int parity, int64_t first, int64_t count,
+                          double* fields, double* partials, int n_records, int32_t x_lo,
+                          int32_t x_hi, hipStream_t stream) {
+    if (first < 0 || count <= 0 || first + count > (int64_t)v.nx * v.ny) return hipErrorInvalidValue;
+    const dim3 grid(blocks_for(count));
     if (partials && (int64_t)grid.x > n_records) return hipErrorInvalidValue;
-    LB_DISPATCH_STORAGE(v.storage, moments_kernel, grid, stream, v, parity, fields, partials,
-                        x_lo, x_hi);
+    LB_DISPATCH_STORAGE(v.storage, moments_kernel, grid, stream, v, parity, first, count, fields,
+                        partials, x_lo, x_hi);
     return hipGetLastError();
 }
 
@@ -1567,5 +1825,7 @@ hipError_t launch_fill(void* dst, uint8_t value, size_t bytes, hipStream_t strea
                        reinterpret_cast<uint8_t*>(dst), value, bytes);
     return hipGetLastError();
 }
+
+#endif  // LB_SWEEP_UNIT
 
 }  // namespace lbm

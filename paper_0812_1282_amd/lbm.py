@@ -46,7 +46,8 @@ class lb_params(ctypes.Structure):
                 ("tau_phi", ctypes.c_double), ("rho_ref", ctypes.c_double),
                 ("collision", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32),
-                ("diag_every", ctypes.c_int32), ("tau_clamp", ctypes.c_int32)]
+                ("diag_every", ctypes.c_int32), ("tau_clamp", ctypes.c_int32),
+                ("inplace", ctypes.c_int32)]
 
 
 class lb_diag(ctypes.Structure):
@@ -145,9 +146,11 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(_D)
 
 
-def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0, diag_every=0):
+def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0, diag_every=0,
+                inplace=0):
     """lb_params from a workload dictionary (see workloads.params). Step 2
-    (zero_u_feq) defaults to on for MRT and off for BGK."""
+    (zero_u_feq) defaults to on for MRT and off for BGK. inplace=1 updates one
+    population buffer in place (f64 and f32)."""
     coll = COLLISION[collision or p["collision"]]
     if zero_u_feq is None:
         zero_u_feq = 1 if coll == MRT else 0
@@ -155,7 +158,7 @@ def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0,
                      p["tau_alpha"], p["tau_beta"], p["tau_phi"], p.get("rho_ref", 1.0),
                      coll, STORAGE[storage] if isinstance(storage, str) else int(storage),
                      int(zero_u_feq), int(zero_u_geq), int(diag_every),
-                     int(p.get("tau_clamp", 0)))
+                     int(p.get("tau_clamp", 0)), int(inplace))
 
 
 def _torch_stream():

@@ -28,7 +28,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ("csrc/lb_kernels.hip", "csrc/lb_internal.h", "csrc/lb_api.hip")
 STORAGE_NAMES = {0: "f64", 1: "f32", 2: "f16s", 3: "bf16s", 4: "f64c", 5: "f32c"}
 # Algorithmic bytes per lattice update: every population read once and written once.
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104}
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104,
+                "f64ip": 288, "f32ip": 144}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -40,16 +41,20 @@ def source_hash():
     return h.hexdigest()
 
 
-_SWEEP = re.compile(r"sweep_kernel<\s*(\d+)\s*,\s*(\d+)\s*,\s*(\d+)\s*,\s*(\w+)\s*,\s*(\w+)\s*>")
+_SWEEP = re.compile(r"sweep_kernel<\s*(\d+)\s*,\s*(\d+)\s*,\s*(\d+)\s*,\s*(\w+)\s*,\s*(\w+)"
+                    r"\s*(?:,\s*(\d+)\s*)?>")
 
 
 def sweep_key(name):
-    """(storage, collision, block_x, diag, tau_phi_one) of a sweep kernel name, else None."""
+    """(storage, collision, block_x, diag, tau_phi_one) of a sweep kernel name, else None.
+    The in-place phases (read mode 1, 2) are named storage + "ip"."""
     m = _SWEEP.search(name)
     if not m:
         return None
-    return (STORAGE_NAMES.get(int(m.group(1)), m.group(1)), int(m.group(2)), int(m.group(3)),
-            m.group(4) == "true", m.group(5) == "true")
+    st = STORAGE_NAMES.get(int(m.group(1)), m.group(1))
+    if m.group(6) and int(m.group(6)) > 0:
+        st += "ip"
+    return (st, int(m.group(2)), int(m.group(3)), m.group(4) == "true", m.group(5) == "true")
 
 
 def short_name(name):

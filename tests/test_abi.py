@@ -60,10 +60,47 @@ def test_compressed_formats_need_tau_phi_one(storage):
     assert e.value.code == lbm.LB_EINVAL
 
 
+def test_inplace_workspace_is_one_buffer_plus_a_plane():
+    for st in ("f64", "f32"):
+        p = wl.params(1000, 500)
+        two = lbm.lb_workspace_bytes(lbm.make_params(p, st))
+        one = lbm.lb_workspace_bytes(lbm.make_params(p, st, inplace=1))
+        per = {"f64": 144, "f32": 72}[st]
+        nodes = 1024 * 500  # rows padded to a multiple of 64
+        assert two - one == per * nodes - 8 * nodes, (st, two, one)
+
+
+@pytest.mark.parametrize("storage", ["F16S", "BF16S", "F64C", "F32C"])
+def test_inplace_only_for_f64_and_f32(storage):
+    p = lbm.lb_params()
+    lbm.load_library().lb_default_params(16, 8, ctypes.byref(p))
+    p.storage = getattr(lbm, storage)
+    p.inplace = 1
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_workspace_bytes(p)
+    assert e.value.code == lbm.LB_EINVAL
+
+
+def test_inplace_rejected_in_batches():
+    """Rejected while validating, before any device work."""
+    p = wl.params(8, 6)
+    inp = wl.random_fields(p, seed=0)
+    P = (lbm.lb_params * 1)(lbm.make_params(p, "f32", inplace=1))
+    solid = np.ascontiguousarray(inp["solid"], dtype=np.uint8)
+    phi0 = np.ascontiguousarray(inp["phi0"], dtype=np.float64)
+    solids = (ctypes.POINTER(ctypes.c_uint8) * 1)(solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    phis = (ctypes.POINTER(ctypes.c_double) * 1)(phi0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    h = ctypes.c_void_p()
+    rc = lbm.load_library().lb_batch_init(1, P, solids, None, phis, None, None, None, None, None,
+                                          ctypes.byref(h))
+    assert rc == lbm.LB_EINVAL and not h.value
+    assert b"single lattices" in lbm.load_library().lb_last_error()
+
+
 @pytest.mark.parametrize("field,value", [
     ("nx", 2), ("ny", 0), ("tau_alpha", 0.5), ("tau_beta", 0.3), ("tau_phi", 0.5),
     ("collision", 7), ("storage", 9), ("zero_u_feq", 2), ("diag_every", -1), ("tau_clamp", 2),
-    ("kappa", float("nan")), ("rho_ref", 0.0),
+    ("inplace", 2), ("kappa", float("nan")), ("rho_ref", 0.0),
 ])
 def test_init_rejects_bad_params_before_any_device_work(field, value):
     p = wl.params(8, 6)
