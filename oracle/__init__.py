@@ -29,7 +29,8 @@ class OrcParams(ctypes.Structure):
                 ("tau_phi", ctypes.c_double),
                 ("collision", ctypes.c_int32),
                 ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32),
-                ("tau_clamp", ctypes.c_int32)]
+                ("tau_clamp", ctypes.c_int32), ("tau_lut", ctypes.c_int32),
+                ("bounce", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +67,8 @@ def lib():
     L.orc_equilibria_node.argtypes = [P] + [ctypes.c_double] * 9 + [_D, _D]
     L.orc_collide_node.argtypes = [P, ctypes.c_double, _D, _D, _D, _D, _D, _D]
     L.orc_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, _U8, _D, _D]
+    L.orc_stream_lattice_node.argtypes = [ctypes.c_int32, ctypes.c_int32, _U8, _D, _D]
+    L.orc_reflect_walls.argtypes = [ctypes.c_int32, ctypes.c_int32, _U8, _D, _D]
     L.orc_tau.restype = ctypes.c_double
     L.orc_tau.argtypes = [P, ctypes.c_double]
     L.orc_set_threads.argtypes = [ctypes.c_int32]
@@ -89,12 +92,14 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, A=-0.04, B=0.04, kappa=0.04, Gamma=0.1, tau_alpha=1.0,
                 tau_beta=1.0, tau_phi=1.0, collision=BGK, zero_u_feq=None,
-                zero_u_geq=0, tau_clamp=0):
-    """Oracle parameters; Step 2 defaults to on for MRT and off for BGK."""
+                zero_u_geq=0, tau_clamp=0, tau_lut=0, bounce=0):
+    """Oracle parameters; Step 2 defaults to on for MRT and off for BGK.
+    tau_lut >= 2: tau from the table of Sec. VI; bounce = 1: lattice-node
+    bounce-back (Fig. 9b)."""
     if zero_u_feq is None:
         zero_u_feq = 1 if collision == MRT else 0
     return OrcParams(nx, ny, A, B, kappa, Gamma, tau_alpha, tau_beta, tau_phi,
-                     collision, zero_u_feq, zero_u_geq, tau_clamp)
+                     collision, zero_u_feq, zero_u_geq, tau_clamp, tau_lut, bounce)
 
 
 class Oracle:
@@ -236,6 +241,27 @@ def stream(solid, post):
     nxt = np.zeros((9, ny, nx))
     lib().orc_stream(nx, ny, solid.ctypes.data_as(_U8), _dp(post), _dp(nxt))
     return nxt
+
+
+def stream_lattice_node(solid, post):
+    """Lattice-node streaming (Fig. 9b) of a (9, ny, nx) post-collision set."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8)
+    ny, nx = solid.shape
+    post = _f64(post)
+    out = np.zeros_like(post)
+    lib().orc_stream_lattice_node(nx, ny, solid.ctypes.data_as(_U8), _dp(post), _dp(out))
+    return out
+
+
+def reflect_walls(solid, pre, post=None):
+    """Wall nodes' reversal (Fig. 9b): post_i = pre_opp(i) at every wall node;
+    other nodes keep the values of post (zeros if None)."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8)
+    ny, nx = solid.shape
+    pre = _f64(pre)
+    out = np.zeros_like(pre) if post is None else np.array(post, dtype=np.float64)
+    lib().orc_reflect_walls(nx, ny, solid.ctypes.data_as(_U8), _dp(pre), _dp(out))
+    return out
 
 
 def tau(params, phi):

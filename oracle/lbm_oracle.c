@@ -32,6 +32,18 @@
  *    phi to [-1, 1] first, for runs where phi overshoots a bulk value whose
  *    tau is close to 1/2.
  *  - bounce-back applies to g as well as to f.
+ *  - lattice-node bounce-back (Fig. 9b, option): a wall node is a solid node
+ *    with a fluid node among its eight neighbours. It holds the populations
+ *    that streamed into it and, in place of a collision, reverses them, so a
+ *    population sent into the wall returns to the node it left two steps
+ *    later (one with mid-link). At S_0 a wall node holds what its fluid
+ *    neighbours' equilibria send into it; populations between wall nodes stay
+ *    zero. Mass is then conserved over fluid and wall nodes together.
+ *  - the tau table of Sec. VI (option): tau_lut values of tau evenly spaced
+ *    from tau_beta to tau_alpha (viscosity is linear in tau, so the spacing is
+ *    even in viscosity too); a node takes the entry closest to its Eq. (tau)
+ *    value, the lower-index entry on a tie, which also limits tau to the
+ *    bulk range.
  *  - the stencil for d/dy is the printed d/dx stencil rotated by 90 degrees.
  */
 #include "lbm_oracle.h"
@@ -208,9 +220,30 @@ void orc_gradients(int32_t nx, int32_t ny, const uint8_t* solid, const double* p
 
 /* Eq. (tau): linear in the node's phi; with tau_clamp, phi is first limited to
  * the bulk range [-1, 1]. */
+static double lut_entry(const orc_params* p, int k) {
+    return p->tau_beta + k * ((p->tau_alpha - p->tau_beta) / (p->tau_lut - 1));
+}
+
 double orc_tau(const orc_params* p, double phi) {
     if (p->tau_clamp) phi = phi > 1.0 ? 1.0 : (phi < -1.0 ? -1.0 : phi);
-    return p->tau_beta + 0.5 * (phi + 1.0) * (p->tau_alpha - p->tau_beta);
+    const double tau = p->tau_beta + 0.5 * (phi + 1.0) * (p->tau_alpha - p->tau_beta);
+    if (p->tau_lut < 2) return tau;
+    /* Sec. VI: the closest entry of the table. The entries run monotonically
+     * from tau_beta to tau_alpha; bisect for the last one not past tau, then
+     * take it or the next, whichever is closer (the first on a tie). */
+    const double dir = p->tau_alpha >= p->tau_beta ? 1.0 : -1.0;
+    int lo = 0, hi = p->tau_lut - 1;
+    if (dir * (lut_entry(p, lo) - tau) >= 0.0) return lut_entry(p, lo);
+    if (dir * (lut_entry(p, hi) - tau) <= 0.0) return lut_entry(p, hi);
+    while (hi - lo > 1) {
+        const int mid = lo + (hi - lo) / 2;
+        if (dir * (lut_entry(p, mid) - tau) <= 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return fabs(lut_entry(p, hi) - tau) < fabs(tau - lut_entry(p, lo)) ? lut_entry(p, hi)
+                                                                        : lut_entry(p, lo);
 }
 
 /* Appendix A, Eqs. (equilibrium) and (feq0), with c = 1, and Eqs. (chempot), (p0)
@@ -298,6 +331,47 @@ void orc_stream(int32_t nx, int32_t ny, const uint8_t* solid, const double* post
         }
 }
 
+/* A solid node with a fluid node among its eight neighbours. */
+static int is_wall(int32_t nx, int32_t ny, const uint8_t* solid, int x, int y) {
+    if (!solid[(size_t)y * nx + x]) return 0;
+    for (int k = 1; k < 9; ++k)
+        if (!solid[(size_t)wrap(y + EY[k], ny) * nx + wrap(x + EX[k], nx)]) return 1;
+    return 0;
+}
+
+/* Lattice-node bounce-back, the wall nodes' part: each reverses the
+ * populations it holds (post_i = pre_opp(i)) in place of a collision. */
+void orc_reflect_walls(int32_t nx, int32_t ny, const uint8_t* solid, const double* pre,
+                       double* post) {
+    static const int OPP[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+    const size_t n = (size_t)nx * ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (!is_wall(nx, ny, solid, x, y)) continue;
+            const size_t r = (size_t)y * nx + x;
+            for (int i = 0; i < 9; ++i) post[OPP[i] * n + r] = pre[i * n + r];
+        }
+}
+
+/* Eqs. (stream1)/(stream2) with lattice-node bounce-back: every population of
+ * a fluid or wall node moves along e_i to the next node; one that would enter
+ * the interior of a solid (only a wall node can send it there) is dropped. */
+void orc_stream_lattice_node(int32_t nx, int32_t ny, const uint8_t* solid, const double* post,
+                             double* next) {
+    const size_t n = (size_t)nx * ny;
+    memset(next, 0, 9 * n * sizeof(double));
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t r = (size_t)y * nx + x;
+            if (solid[r] && !is_wall(nx, ny, solid, x, y)) continue;
+            for (int i = 0; i < 9; ++i) {
+                const int qx = wrap(x + EX[i], nx), qy = wrap(y + EY[i], ny);
+                const size_t q = (size_t)qy * nx + qx;
+                if (!solid[q] || is_wall(nx, ny, solid, qx, qy)) next[i * n + q] = post[i * n + r];
+            }
+        }
+}
+
 static int all_finite(const double* a, size_t n) {
     if (!a) return 1;
     for (size_t i = 0; i < n; ++i)
@@ -336,6 +410,7 @@ orc_state* orc_create(const orc_params* p, const uint8_t* solid, const double* d
                       const double* uy0) {
     if (!p || !solid || !phi0 || p->nx < 3 || p->ny < 3) return NULL;
     if (!(p->tau_alpha > 0.5) || !(p->tau_beta > 0.5) || !(p->tau_phi > 0.5)) return NULL;
+    if ((p->bounce != 0 && p->bounce != 1) || p->tau_lut < 0 || p->tau_lut == 1) return NULL;
     const size_t n = (size_t)p->nx * p->ny;
     if (!all_finite(phi0, n) || !all_finite(rho0, n) || !all_finite(ux0, n) ||
         !all_finite(uy0, n) || !all_finite(dphi, n))
@@ -373,6 +448,20 @@ orc_state* orc_create(const orc_params* p, const uint8_t* solid, const double* d
     }
     /* S_0: equilibria of the initial fields with their own velocity. */
     equilibria_field(s, 0, s->f, s->g);
+    if (p->bounce == 1) {
+        /* wall nodes: what the fluid equilibria send into them */
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (!is_wall(nx, ny, s->solid, x, y)) continue;
+                const size_t w = (size_t)y * nx + x;
+                for (int i = 1; i < 9; ++i) {
+                    const size_t q = (size_t)wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx);
+                    if (s->solid[q]) continue;
+                    s->f[i * n + w] = s->f[i * n + q];
+                    s->g[i * n + w] = s->g[i * n + q];
+                }
+            }
+    }
     return s;
 }
 
@@ -425,8 +514,15 @@ void orc_step(orc_state* s, int64_t nsteps) {
                 }
             }
         /* Step 4: streaming with bounce-back. */
-        orc_stream(nx, ny, s->solid, s->fpost, s->f);
-        orc_stream(nx, ny, s->solid, s->gpost, s->g);
+        if (p->bounce == 1) {
+            orc_reflect_walls(nx, ny, s->solid, s->f, s->fpost);
+            orc_reflect_walls(nx, ny, s->solid, s->g, s->gpost);
+            orc_stream_lattice_node(nx, ny, s->solid, s->fpost, s->f);
+            orc_stream_lattice_node(nx, ny, s->solid, s->gpost, s->g);
+        } else {
+            orc_stream(nx, ny, s->solid, s->fpost, s->f);
+            orc_stream(nx, ny, s->solid, s->gpost, s->g);
+        }
         s->step += 1;
     }
 }

@@ -43,6 +43,10 @@ typedef struct {
     int32_t zero_u_feq;   /* Step 2: u = 0 at boundary nodes in f^eq */
     int32_t zero_u_geq;   /* Step 2 applied to g^eq as well */
     int32_t tau_clamp;    /* 1: phi clamped to [-1, 1] inside Eq. (tau); 0: the law as printed */
+    int32_t tau_lut;      /* >= 2: tau taken from a table of this many values (Sec. VI);
+                             0: Eq. (tau) itself */
+    int32_t bounce;       /* 0: mid-link bounce-back (Fig. 9a); 1: lattice-node
+                             bounce-back (Fig. 9b), the wall on the boundary nodes */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -86,6 +90,10 @@ void orc_collide_node(const orc_params* p, double phi, const double f[9],
                       double fpost[9], double gpost[9]);
 void orc_stream(int32_t nx, int32_t ny, const uint8_t* solid, const double* post,
                 double* next);
+void orc_stream_lattice_node(int32_t nx, int32_t ny, const uint8_t* solid, const double* post,
+                             double* next);
+void orc_reflect_walls(int32_t nx, int32_t ny, const uint8_t* solid, const double* pre,
+                       double* post);
 double orc_tau(const orc_params* p, double phi);
 
 void orc_set_threads(int32_t n);

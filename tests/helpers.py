@@ -13,7 +13,8 @@ def orc_params(p, **over):
                               collision=COLL[q["collision"]],
                               zero_u_feq=q.get("zero_u_feq"),
                               zero_u_geq=q.get("zero_u_geq", 0),
-                              tau_clamp=q.get("tau_clamp", 0))
+                              tau_clamp=q.get("tau_clamp", 0),
+                              tau_lut=q.get("tau_lut", 0), bounce=q.get("bounce", 0))
 
 
 def make_oracle(p, inp, **over):
