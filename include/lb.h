@@ -115,7 +115,24 @@ typedef struct {
                              buffer is needed; the phi of the nodes along tile borders
                              is formed by a pre-pass into a plane of 8 bytes per node.
                              Results are bit-identical to inplace = 0. */
+    int32_t tau_lut;      /* 0: tau from Eq. (tau). n >= 2 (at most 2^24): the table
+                             of Sec. VI, n values of tau evenly spaced from tau_beta
+                             to tau_alpha (evenly in viscosity too); each node takes
+                             the entry nearest its Eq. (tau) value, the lower one on
+                             a tie (so tau stays within the bulk range) */
+    int32_t bounce;       /* LB_MIDLINK or LB_LATTICE_NODE */
 } lb_params;
+
+/* Wall treatment (lb_params.bounce). LB_MIDLINK: mid-link bounce-back (Sec. V.B,
+ * Fig. 9a). LB_LATTICE_NODE: the wall lies on the boundary nodes (Fig. 9b): a
+ * solid node with a fluid neighbour keeps the populations that stream into it
+ * and sends each back the way it came on the next step, so a population
+ * returns to the node it left after two steps; at S_0 it holds what the
+ * equilibria of its fluid neighbours send into it. LB_F64 and LB_F32 with
+ * inplace = 0. Mass is conserved over fluid and wall nodes together; the sums
+ * of lb_diagnostics cover the fluid nodes only. */
+#define LB_MIDLINK 0
+#define LB_LATTICE_NODE 1
 
 typedef struct {
     double sum_rho;       /* FP64 sum of rho over fluid nodes of S_n */

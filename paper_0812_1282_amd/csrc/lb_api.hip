@@ -169,6 +169,14 @@ int validate_params(const lb_params* p) {
     if (p->inplace != 0 && p->inplace != 1) return fail(LB_EINVAL, "inplace must be 0 or 1");
     if (p->inplace && p->storage != LB_F64 && p->storage != LB_F32)
         return fail(LB_EINVAL, "in-place update is available for LB_F64 and LB_F32");
+    if (p->tau_lut < 0 || p->tau_lut == 1 || p->tau_lut > (1 << 24))
+        return fail(LB_EINVAL, "tau_lut must be 0 or 2 .. 2^24");
+    if (p->bounce != LB_MIDLINK && p->bounce != LB_LATTICE_NODE)
+        return fail(LB_EINVAL, "bounce must be LB_MIDLINK or LB_LATTICE_NODE");
+    if (p->bounce == LB_LATTICE_NODE &&
+        (p->inplace || (p->storage != LB_F64 && p->storage != LB_F32)))
+        return fail(LB_EINVAL, "lattice-node bounce-back is available for LB_F64 and LB_F32 "
+                               "with inplace = 0");
     // One row block of the populations is addressed through a buffer
     // descriptor with a 32-bit record count.
     if ((int64_t)((p->nx + 63) / 64) * 64 * 18 * 8 >= ((int64_t)1 << 31))
@@ -296,6 +304,9 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
     v.buf[1] = mb.base + L.off_buf1;
     v.band = p->inplace ? mb.base + L.off_band : nullptr;
     v.inplace = p->inplace;
+    v.tau_lut = p->tau_lut;
+    v.bounce = p->bounce;
+    v.tau_step = p->tau_lut > 1 ? (p->tau_alpha - p->tau_beta) / (p->tau_lut - 1) : 0.0;
     v.nbr = reinterpret_cast<const uint8_t*>(mb.base + L.off_nbr);
     v.grec = reinterpret_cast<const uint8_t*>(mb.base + L.off_grec);
     v.dphi = mb.base + L.off_dphi;

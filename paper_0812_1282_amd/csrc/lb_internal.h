@@ -71,6 +71,8 @@ struct View {
     int32_t zero_u_feq, zero_u_geq;
     int32_t storage, collision;
     int32_t tau_clamp, inplace;
+    int32_t tau_lut, bounce;  // tau table size (0 = Eq. (tau)); lattice-node bounce-back
+    double tau_step;          // (tau_alpha - tau_beta) / (tau_lut - 1)
 };
 
 struct Tile {

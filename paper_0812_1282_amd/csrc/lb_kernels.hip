@@ -528,6 +528,14 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     char* dst = parity ? v.buf[0] : v.buf[1];
 
     const int t = threadIdx.x;
+    // With lattice-node bounce-back the fluid nodes pull across every link
+    // (the solid neighbour is a wall node holding the population), so the
+    // mid-link bounce bits are dropped from the pulls.
+    constexpr bool kWallNodes = (S == ST_F64 || S == ST_F32) && M == 0;
+    auto pull_mask = [&](uint32_t m) -> uint32_t {
+        if constexpr (kWallNodes) return v.bounce ? 0u : m;
+        return m;
+    };
     const int x0 = tx * BX;
     const int y0 = ty * rows;
     const int y1 = min(y0 + rows, ny);
@@ -574,9 +582,9 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             for (int i = 0; i < 9; ++i) small += g[i];
             return base + small;
         } else if constexpr (G1) {
-            return phi9<S, M>(R, v, c, nb, small, base);
+            return phi9<S, M>(R, v, c, pull_mask(nb), small, base);
         } else {
-            pull9<S, 9, M>(R, v, c, nb, g, &base);
+            pull9<S, 9, M>(R, v, c, pull_mask(nb), g, &base);
 #pragma unroll
             for (int i = 0; i < 9; ++i) small += g[i];
             return base + small;
@@ -714,10 +722,29 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 f[3] = (nb & 4u) ? ldp<S, 4>(R.r[0], v, co, 0) : ldp<S, 3>(R.r[1], v, co, 0);
             }
         } else {
-            if (work) pull9<S, 0, M>(R, v, co, nb, f);
+            if (work) pull9<S, 0, M>(R, v, co, pull_mask(nb), f);
         }
         fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         __syncthreads();
+        if constexpr (kWallNodes) {
+            // Lattice-node bounce-back: a solid node with fluid neighbours
+            // returns what each sent it along the reverse link (plane OPP(j)
+            // at the wall node, pulled by that neighbour at the next step).
+            if (v.bounce && active && nb == 0xFFu) {
+                const uint32_t fl = grec[(size_t)y * v.pitch + x];
+                if (fl != 0u) {
+                    const Rsrc out = row_rsrc(dst, v, y);
+                    static_for<8>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value + 1;
+                        if ((fl >> (OPP[j] - 1)) & 1u) {  // source w - e_j is fluid
+                            constexpr int r = src_row<0, j>(), c = src_col<0, j>();
+                            stp<S, OPP[j]>(out, v, co, ldp<S, j>(R.r[r], v, co, c));
+                            stp<S, 9 + OPP[j]>(out, v, co, ldp<S, 9 + j>(R.r[r], v, co, c));
+                        }
+                    });
+                }
+            }
+        }
         if (!work) return;
 
         const int c = t + 2;
@@ -804,8 +831,19 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                             ph * ph * (rA * (real)0.5 + rB * (real)0.75 * ph * ph);
             basef = p0 - rK * ph * lap;
         }
-        const real pt = !v.tau_clamp ? ph : (ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph));
-        const real tau = tb + (real)0.5 * (pt + (real)1) * (ta - tb);
+        real tau;
+        if (v.tau_lut > 1) {
+            // Sec. VI table: entry k = nearest to the Eq. (tau) value, i.e. to
+            // position (phi + 1) / 2 (n - 1) along the table, lower on a tie.
+            const real tn = (real)(v.tau_lut - 1);
+            real pos = (ph + (real)1) * (real)0.5 * tn;
+            pos = pos < (real)0 ? (real)0 : (pos > tn ? tn : pos);
+            tau = tb + ceil(pos - (real)0.5) * (real)v.tau_step;
+        } else {
+            const real pt =
+                !v.tau_clamp ? ph : (ph > (real)1 ? (real)1 : (ph < (real)-1 ? (real)-1 : ph));
+            tau = tb + (real)0.5 * (pt + (real)1) * (ta - tb);
+        }
         const real omega = recip(tau);
 
         // Step 2: u = 0 at boundary nodes in the equilibria (flags).
@@ -1387,7 +1425,8 @@ __device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, do
             return true;
         }
     }
-    pull9<S, 0>(R, v, co, nb, a);
+    const uint32_t nbp = ((S == ST_F64 || S == ST_F32) && v.bounce) ? 0u : nb;
+    pull9<S, 0>(R, v, co, nbp, a);
     if constexpr (Fmt<S>::gstate) {
         // g of S_n from the stored g-state: g_i = g^eq_i of r - e_i (or of r in
         // the opposite direction across a solid link), g_0 = phi - sum g^eq_i.
@@ -1431,7 +1470,7 @@ __device__ inline bool pull_node_abs(const View& v, int parity, int x, int y, do
         for (int i = 1; i < 9; ++i) g[i] = (double)b[i];
         return true;
     }
-    pull9<S, 9>(R, v, co, nb, b, &base);
+    pull9<S, 9>(R, v, co, nbp, b, &base);
     for (int i = 0; i < 9; ++i) {
         f[i] = (double)a[i] + rest_f(v, i);
         g[i] = (double)b[i];
@@ -1563,9 +1602,26 @@ __global__ __launch_bounds__(256) void init_kernel(View v, const double* __restr
             return;
         }
     }
+    // Lattice-node bounce-back: no value waits across a solid link (the wall
+    // node holds it), and the wall node's first pull finds what this node's
+    // equilibrium sends into it, at r in the plane of that direction.
+    bool lnode = false;
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        lnode = v.bounce != 0;
+        if (lnode) {
+            const ColOff oco = col_offsets<S>((uint32_t)x, (uint32_t)x, (uint32_t)x);
+            static_for<8>([&](auto jc) {
+                constexpr int j = decltype(jc)::value + 1;
+                if ((nb >> (OPP[j] - 1)) & 1u) {  // r + e_j is solid
+                    stp<S, j>(own, v, oco, (R)(feq[j] - rest_f(v, j)));
+                    stp<S, 9 + j>(own, v, oco, (R)geq[j]);
+                }
+            });
+        }
+    }
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const bool bb = i > 0 && ((nb >> (i - 1)) & 1u);
+        const bool bb = !lnode && i > 0 && ((nb >> (i - 1)) & 1u);
         // Across a solid link the value waits at r in the opposite direction's plane.
         const int xs = bb ? x : wrap(x - EX[i], nx), ys = bb ? y : wrap(y - EY[i], ny);
         const Rsrc row = row_rsrc(dst, v, ys);

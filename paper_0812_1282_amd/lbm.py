@@ -20,6 +20,7 @@ BGK, MRT = 0, 1
 F64, F32, F16S, BF16S, F64C, F32C = 0, 1, 2, 3, 4, 5
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S, "f64c": F64C, "f32c": F32C}
 COLLISION = {"bgk": BGK, "mrt": MRT}
+MIDLINK, LATTICE_NODE = 0, 1
 
 EXPORTS = [
     "lb_default_params", "lb_workspace_bytes", "lb_init", "lb_init_ext", "lb_step",
@@ -47,7 +48,8 @@ class lb_params(ctypes.Structure):
                 ("collision", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("zero_u_feq", ctypes.c_int32), ("zero_u_geq", ctypes.c_int32),
                 ("diag_every", ctypes.c_int32), ("tau_clamp", ctypes.c_int32),
-                ("inplace", ctypes.c_int32)]
+                ("inplace", ctypes.c_int32), ("tau_lut", ctypes.c_int32),
+                ("bounce", ctypes.c_int32)]
 
 
 class lb_diag(ctypes.Structure):
@@ -150,7 +152,8 @@ def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0,
                 inplace=0):
     """lb_params from a workload dictionary (see workloads.params). Step 2
     (zero_u_feq) defaults to on for MRT and off for BGK. inplace=1 updates one
-    population buffer in place (f64 and f32)."""
+    population buffer in place (f64 and f32). The workload's "tau_lut" (table
+    size, 0 = off) and "bounce" (MIDLINK or LATTICE_NODE) are passed through."""
     coll = COLLISION[collision or p["collision"]]
     if zero_u_feq is None:
         zero_u_feq = 1 if coll == MRT else 0
@@ -158,7 +161,8 @@ def make_params(p, storage="f64", collision=None, zero_u_feq=None, zero_u_geq=0,
                      p["tau_alpha"], p["tau_beta"], p["tau_phi"], p.get("rho_ref", 1.0),
                      coll, STORAGE[storage] if isinstance(storage, str) else int(storage),
                      int(zero_u_feq), int(zero_u_geq), int(diag_every),
-                     int(p.get("tau_clamp", 0)), int(inplace))
+                     int(p.get("tau_clamp", 0)), int(inplace), int(p.get("tau_lut", 0)),
+                     int(p.get("bounce", 0)))
 
 
 def _torch_stream():

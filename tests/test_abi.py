@@ -81,6 +81,15 @@ def test_inplace_only_for_f64_and_f32(storage):
     assert e.value.code == lbm.LB_EINVAL
 
 
+@pytest.mark.parametrize("storage,inplace", [("f16s", 0), ("f64c", 0), ("f32c", 0), ("f32", 1)])
+def test_lattice_node_bounce_back_formats(storage, inplace):
+    p = dict(wl.params(16, 8), tau_phi=1.0, bounce=lbm.LATTICE_NODE)
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_workspace_bytes(lbm.make_params(p, storage, inplace=inplace))
+    assert e.value.code == lbm.LB_EINVAL
+    assert lbm.lb_workspace_bytes(lbm.make_params(p, "f32")) > 0
+
+
 def test_inplace_rejected_in_batches():
     """Rejected while validating, before any device work."""
     p = wl.params(8, 6)
@@ -100,7 +109,8 @@ def test_inplace_rejected_in_batches():
 @pytest.mark.parametrize("field,value", [
     ("nx", 2), ("ny", 0), ("tau_alpha", 0.5), ("tau_beta", 0.3), ("tau_phi", 0.5),
     ("collision", 7), ("storage", 9), ("zero_u_feq", 2), ("diag_every", -1), ("tau_clamp", 2),
-    ("inplace", 2), ("kappa", float("nan")), ("rho_ref", 0.0),
+    ("inplace", 2), ("tau_lut", 1), ("tau_lut", -3), ("tau_lut", (1 << 24) + 1), ("bounce", 2),
+    ("kappa", float("nan")), ("rho_ref", 0.0),
 ])
 def test_init_rejects_bad_params_before_any_device_work(field, value):
     p = wl.params(8, 6)

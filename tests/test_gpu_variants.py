@@ -1,0 +1,149 @@
+"""The paper's two variants on the HIP path, held to the FP64 oracle: the tau
+table of Sec. VI (lb_params.tau_lut) and lattice-node bounce-back (Fig. 9b,
+lb_params.bounce = LB_LATTICE_NODE). FP64 at the FP64 tolerance; FP32 at the
+reduced-precision gate; results independent of the tile shape; batch members
+equal to solo runs."""
+import numpy as np
+import pytest
+
+from oracle import analysis
+from paper_0812_1282_amd import lbm, workloads as wl
+from tests.helpers import make_oracle
+from tests.test_gpu_parity import D60, compare, gpu_lattice, run_pair, say
+
+pytestmark = pytest.mark.gpu
+
+LN = lbm.LATTICE_NODE
+
+
+def random_case(collision, seed=11, nx=70, ny=30, **over):
+    p = dict(wl.params(nx, ny, 1.3, 0.6, collision, Gamma=0.3, tau_phi=0.8), **over)
+    inp = wl.random_fields(p, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    inp["dphi"] = np.where(inp["solid"] != 0, rng.uniform(-0.3, 0.3, inp["solid"].shape), 0.0)
+    return p, inp
+
+
+@pytest.mark.parametrize("n", [10000, 3])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_tau_table_random_fields(n, collision):
+    p, inp = random_case(collision, tau_lut=n)
+    run_pair(p, inp, 200, what=f"tau table n={n} {collision}")
+
+
+def test_tau_table_c2_drop_viscosity_ratio():
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(60.0, 0.04, 0.04), seed=201)
+    p = dict(p, tau_lut=10000)
+    run_pair(p, inp, 1000, what="C2 256x128 mrt 60deg tau table")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_tau_table_reduced_precision(storage):
+    dphi = analysis.theory_dphi(60.0, 0.04, 0.04)
+    p, inp = wl.c5_member(dict(nx=128, ny=64, tau_beta=0.55, seed=777), dphi)
+    p = dict(p, tau_lut=10000)
+    say(f"case tau table {storage}")
+    lat = gpu_lattice(p, inp, storage)
+    lbm.lb_step(lat, 3000)
+    orc = make_oracle(p, inp)
+    orc.step(3000)
+    fluid = inp["solid"] == 0
+    d = np.abs(lbm.lb_read_fields(lat)[0] - orc.fields()[0])[fluid].max()
+    say(f"  max|dphi| {d:.2e}")
+    assert d <= 1e-3
+    lat.close()
+
+
+def test_lattice_node_c1_drop():
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    run_pair(dict(p, bounce=LN), inp, 1000, what="C1 100x50 BGK lattice-node")
+
+
+@pytest.mark.parametrize("collision,zf,zg", [("bgk", 0, 0), ("mrt", 1, 0), ("mrt", 1, 1),
+                                             ("mrt", 0, 0)])
+def test_lattice_node_every_term(collision, zf, zg):
+    p, inp = random_case(collision, bounce=LN)
+    run_pair(p, inp, 201, what=f"random {collision} lattice-node step2={zf}/{zg}",
+             zero_u_feq=zf, zero_u_geq=zg)
+
+
+def test_lattice_node_with_tau_table_and_viscosity_ratio():
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(120.0, 0.04, 0.04), seed=201)
+    run_pair(dict(p, bounce=LN, tau_lut=10000), inp, 1000,
+             what="C2 256x128 mrt 120deg lattice-node + table")
+
+
+def test_lattice_node_scattered_solids():
+    p = dict(wl.params(48, 40, 1.0, 0.6, "mrt"), bounce=LN)
+    inp = wl.random_fields(p, seed=5)
+    rng = np.random.default_rng(6)
+    solid = inp["solid"].copy()
+    solid[rng.integers(2, 38, 60), rng.integers(0, 48, 60)] = 1
+    solid[10, 5] = 1
+    solid[11, 6] = 1
+    fluid = solid == 0
+    inp = {k: (np.where(fluid, v, 0.0) if isinstance(v, np.ndarray) and k != "solid" else v)
+           for k, v in inp.items()}
+    inp["solid"] = solid
+    inp["dphi"] = np.where(solid != 0, rng.uniform(-0.3, 0.3, solid.shape), 0.0)
+    run_pair(p, inp, 300, what="scattered solids lattice-node")
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 5), (67, 13), (130, 7)])
+def test_lattice_node_ragged_sizes_and_tunings(nx, ny):
+    p = dict(wl.params(nx, ny, 1.0, 0.65, "mrt"), bounce=LN)
+    inp = wl.random_fields(p, seed=nx * 100 + ny)
+    inp["dphi"] = wl.wall_field(inp["solid"], 0.1)
+    say(f"case lattice-node ragged {nx}x{ny}")
+    orc = make_oracle(p, inp)
+    orc.step(60)
+    ref = None
+    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3)]:
+        lat = gpu_lattice(p, inp, "f64")
+        lbm.lb_set_tuning(lat, bx, rows)
+        lbm.lb_step(lat, 60)
+        f, g = lbm.lb_read_populations(lat)
+        if ref is None:
+            ref = (f, g)
+            compare(lat, orc, inp["solid"], what=f"lattice-node {nx}x{ny} tile {bx}x{rows}")
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), (bx, rows)
+        lat.close()
+
+
+def test_lattice_node_f32_gate():
+    dphi = analysis.theory_dphi(60.0, 0.04, 0.04)
+    p, inp = wl.c5_member(dict(nx=128, ny=64, tau_beta=0.55, seed=777), dphi)
+    p = dict(p, bounce=LN)
+    say("case lattice-node f32")
+    lat = gpu_lattice(p, inp, "f32")
+    lbm.lb_step(lat, 3000)
+    orc = make_oracle(p, inp)
+    orc.step(3000)
+    fluid = inp["solid"] == 0
+    d = np.abs(lbm.lb_read_fields(lat)[0] - orc.fields()[0])[fluid].max()
+    say(f"  max|dphi| {d:.2e}")
+    assert d <= 1e-3
+    lat.close()
+
+
+def test_variants_in_a_batch_equal_solo_runs():
+    descs = [dict(nx=64, ny=32, theta=45.0, tau_beta=0.6, seed=91),
+             dict(nx=100, ny=40, theta=120.0, tau_beta=0.55, seed=92)]
+    members = []
+    for d, over in zip(descs, ({"bounce": LN}, {"tau_lut": 5000})):
+        p, inp = wl.c5_member(dict(d), analysis.theory_dphi(d["theta"], 0.04, 0.04))
+        members.append((dict(p, **over), inp))
+    say("case batch with variants")
+    b = lbm.lb_batch_init([lbm.make_params(p, "f32") for p, _ in members],
+                          [inp for _, inp in members], tuning=(64, 8))
+    lbm.lb_batch_step(b, 150)
+    for k, (p, inp) in enumerate(members):
+        solo = gpu_lattice(p, inp, "f32")
+        lbm.lb_set_tuning(solo, 128, 16)
+        lbm.lb_step(solo, 150)
+        fb, gb = lbm.lb_batch_read_populations(b, k)
+        fs, gs = lbm.lb_read_populations(solo)
+        assert np.array_equal(fb, fs) and np.array_equal(gb, gs), k
+        solo.close()
+    b.close()
