@@ -467,14 +467,64 @@ def fig5(steps=1_000_000, every=5_000, storage="f64", mobilities=(0.05, 0.1, 0.5
     return out
 
 
+def variants(steps=100_000, angles=(45.0, 60.0, 90.0, 120.0, 135.0), every=20_000):
+    """The paper's variants against its baseline, on the Sec. IV drop (300 x 100,
+    R = 35, tau_alpha = 3, tau_beta = 0.7, Gamma = 0.5): mid-link bounce-back
+    with Eq. (tau) (the baseline), lattice-node bounce-back (Fig. 9b), the
+    10^4-entry tau table (Sec. VI), and both. Each drop starts as the 90-degree
+    semicircle with the wall gradient of the target angle already set and runs
+    `steps` steps; the angle is measured every `every` steps. One FP64 batch per
+    collision operator (all angles and variants as members)."""
+    torch = _torch()
+    kinds = {"midlink": {}, "lattice_node": {"bounce": lbm.LATTICE_NODE},
+             "tau_table": {"tau_lut": 10000},
+             "lattice_node+tau_table": {"bounce": lbm.LATTICE_NODE, "tau_lut": 10000}}
+    out = {"workload": "Sec. IV drop 300x100 R=35, tau 3/0.7, Gamma 0.5", "steps": steps,
+           "runs": []}
+    for coll in ("bgk", "mrt"):
+        members, params, keys = [], [], []
+        for th in angles:
+            dp = lbm.lb_dphi_for_angle(th, KAPPA, -A_LANDAU, A_LANDAU)
+            for kind, over in kinds.items():
+                p, inp = wl.fig2_drop(3.0, 0.7, coll)
+                inp = dict(inp, dphi=np.where(inp["solid"] != 0, dp, 0.0))
+                members.append(inp)
+                params.append(lbm.make_params(dict(p, **over), "f64"))
+                keys.append((th, kind))
+        b = lbm.lb_batch_init(params, members, tuning=(64, 8))
+        hist = {k: [] for k in keys}
+        done, t_run = 0, 0.0
+        while done < steps:
+            t_run += _timed(torch, lambda: lbm.lb_batch_step(b, every))
+            done += every
+            for k, key in enumerate(keys):
+                try:
+                    th = lbm.lb_batch_contact_angle(b, k, 0.0, 300.0, 3.5, 95.5, 0.5, 1)
+                except lbm.LbError:
+                    th = None
+                hist[key].append((done, th))
+        b.close()
+        torch.cuda.empty_cache()
+        for (th, kind), h in hist.items():
+            last = h[-1][1]
+            out["runs"].append({"collision": coll, "theory": th, "variant": kind,
+                                "theta": last, "error": None if last is None else last - th,
+                                "history": h})
+            print(f"variants {coll} {kind:24s} theory {th:6.1f}  theta "
+                  f"{'-' if last is None else round(last, 2)}", flush=True)
+        print(f"variants {coll}: {sum(q.nx * q.ny for q in params) * done / t_run / 1e6:.0f} "
+              f"MLUPS", flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig5"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig5", "variants"])
     ap.add_argument("--out", default="")
     ap.add_argument("--steps", type=int, default=0)
     args = ap.parse_args(argv)
     fn = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "fig2": fig2,
-          "fig5": fig5}[args.which]
+          "fig5": fig5, "variants": variants}[args.which]
     if not args.steps:
         res = fn()
     else:
