@@ -131,6 +131,7 @@ struct Group {
     // cached graphs keyed by whether the graph carries the periodic check
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool batched = false;
+    bool any_walls = false;  // a batch member uses lattice-node bounce-back
 };
 
 struct lb_handle {
@@ -442,6 +443,9 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
         hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
                                     m0.p.tau_phi == 1.0, m0.p.inplace != 0, m0.d_view, nullptr, 0,
                                     gx, gy, g.rows, parity, partials, st);
+        if (e == hipSuccess && m0.p.bounce == LB_LATTICE_NODE)
+            e = launch_walls(m0.p.storage, g.block_x, m0.d_view, nullptr, 0, gx, gy, g.rows,
+                             parity, st);
         if (e != hipSuccess || !diag) return e;
         return launch_finalize(nullptr, nullptr, 1, gx * gy, partials,
                                reinterpret_cast<double*>(m0.base + L.off_diag),
@@ -451,6 +455,9 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
     hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
                                 m0.p.tau_phi == 1.0, false, g.d_views, g.d_tiles, nt, 0, 0, g.rows,
                                 parity, g.d_partials, st);
+    if (e == hipSuccess && g.any_walls)
+        e = launch_walls(m0.p.storage, g.block_x, g.d_views, g.d_tiles, nt, 0, 0, g.rows, parity,
+                         st);
     if (e != hipSuccess || !diag) return e;
     return launch_finalize(g.d_tiles, g.d_first, (int)g.m.size(), 0, g.d_partials, g.d_diag,
                            g.d_flag, st);
@@ -1136,6 +1143,8 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
     lb_batch* b = new lb_batch();
     Group& g = b->g;
     g.batched = true;
+    for (int k = 0; k < n; ++k)
+        if (params[k].bounce == LB_LATTICE_NODE) g.any_walls = true;
     g.stream = reinterpret_cast<hipStream_t>(stream);
     g.block_x = bx;
     g.rows = rows;

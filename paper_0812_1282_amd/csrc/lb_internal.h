@@ -112,6 +112,11 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
                         bool inplace, const View* d_views, const Tile* d_tiles, int n_blocks_1d,
                         int grid_x, int grid_y, int rows, int parity, double* partials,
                         hipStream_t stream);
+// Lattice-node bounce-back: the wall nodes' reversal for one step, over the
+// same tiles as the sweep (members whose bounce is 0 are skipped).
+hipError_t launch_walls(int storage, int block_x, const View* d_views, const Tile* d_tiles,
+                        int n_blocks_1d, int grid_x, int grid_y, int rows, int parity,
+                        hipStream_t stream);
 // In place: phi of S_n at the nodes of the two rows and columns along every
 // tile border of the (block_x, rows) tiling, into View::band.
 hipError_t launch_band(int storage, bool tau_phi_one, const View* d_view, int nx, int ny,

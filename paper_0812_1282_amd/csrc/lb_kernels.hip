@@ -529,11 +529,10 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
 
     const int t = threadIdx.x;
     // With lattice-node bounce-back the fluid nodes pull across every link
-    // (the solid neighbour is a wall node holding the population), so the
-    // mid-link bounce bits are dropped from the pulls.
-    constexpr bool kWallNodes = (S == ST_F64 || S == ST_F32) && M == 0;
+    // (the solid neighbour is a wall node holding the population; wall_kernel
+    // fills it), so the mid-link bounce bits are dropped from the pulls.
     auto pull_mask = [&](uint32_t m) -> uint32_t {
-        if constexpr (kWallNodes) return v.bounce ? 0u : m;
+        if constexpr ((S == ST_F64 || S == ST_F32) && M == 0) return v.bounce ? 0u : m;
         return m;
     };
     const int x0 = tx * BX;
@@ -726,25 +725,6 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         }
         fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         __syncthreads();
-        if constexpr (kWallNodes) {
-            // Lattice-node bounce-back: a solid node with fluid neighbours
-            // returns what each sent it along the reverse link (plane OPP(j)
-            // at the wall node, pulled by that neighbour at the next step).
-            if (v.bounce && active && nb == 0xFFu) {
-                const uint32_t fl = grec[(size_t)y * v.pitch + x];
-                if (fl != 0u) {
-                    const Rsrc out = row_rsrc(dst, v, y);
-                    static_for<8>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value + 1;
-                        if ((fl >> (OPP[j] - 1)) & 1u) {  // source w - e_j is fluid
-                            constexpr int r = src_row<0, j>(), c = src_col<0, j>();
-                            stp<S, OPP[j]>(out, v, co, ldp<S, j>(R.r[r], v, co, c));
-                            stp<S, 9 + OPP[j]>(out, v, co, ldp<S, 9 + j>(R.r[r], v, co, c));
-                        }
-                    });
-                }
-            }
-        }
         if (!work) return;
 
         const int c = t + 2;
@@ -1205,6 +1185,56 @@ __global__ __launch_bounds__(256) void band_kernel(const View* __restrict__ view
     reinterpret_cast<real*>(v.band)[node] = ph;
 }
 
+// Lattice-node bounce-back (Fig. 9b), the wall nodes' part of a step: every
+// solid node with fluid neighbours sends back along each link to a fluid
+// neighbour what that neighbour sent it in the previous step (the post-
+// collision f_j, g_j of r = w - e_j, read from the source buffer), storing it
+// at w in plane OPP(j) of the destination buffer, where r pulls it in the next
+// step. Only wall-node slots are written, so this launch and the sweep of the
+// same step are independent. Tiles as in the sweep; each thread scans one
+// column of its tile.
+template <int S>
+__global__ __launch_bounds__(256) void wall_kernel(const View* __restrict__ views,
+                                                   const Tile* __restrict__ tiles, int rows,
+                                                   int grid_x, int parity) {
+    int member = 0, tx, ty;
+    if (tiles) {
+        const Tile tl = tiles[blockIdx.x];
+        member = tl.member;
+        tx = tl.tx;
+        ty = tl.ty;
+    } else {
+        tx = (int)blockIdx.x % grid_x;
+        ty = (int)blockIdx.x / grid_x;
+    }
+    const View v = views[member];
+    if (!v.bounce) return;
+    const int nx = v.nx, ny = v.ny;
+    const int x = tx * (int)blockDim.x + (int)threadIdx.x;
+    if (x >= nx) return;
+    const char* src = parity ? v.buf[1] : v.buf[0];
+    char* dst = parity ? v.buf[0] : v.buf[1];
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
+    const int y0 = ty * rows, y1 = min(y0 + rows, ny);
+    for (int y = y0; y < y1; ++y) {
+        const size_t node = (size_t)y * v.pitch + x;
+        if (v.nbr[node] != 0xFFu) continue;
+        const uint32_t fl = v.grec[node];  // bit m-1: w + e_m is fluid
+        if (fl == 0u) continue;
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        const Rsrc out = row_rsrc(dst, v, y);
+        static_for<8>([&](auto jc) {
+            constexpr int j = decltype(jc)::value + 1;
+            if ((fl >> (OPP[j] - 1)) & 1u) {  // the source w - e_j is fluid
+                constexpr int r = src_row<0, j>(), c = src_col<0, j>();
+                stp<S, OPP[j]>(out, v, co, ldp<S, j>(R.r[r], v, co, c));
+                stp<S, 9 + OPP[j]>(out, v, co, ldp<S, 9 + j>(R.r[r], v, co, c));
+            }
+        });
+    }
+}
+
 // ------------------------------------------------------------------ sweep launchers
 // The sweep and band kernels of one storage format are instantiated by
 // sweep_fmt<S> / band_fmt<S>; the build compiles this file once per format with
@@ -1291,12 +1321,25 @@ hipError_t band_fmt(bool g1, int parity, dim3 grid, const View* v, BandArgs b, h
     return hipErrorInvalidValue;
 }
 
+template <int S>
+hipError_t wall_fmt(const SweepArgs& a) {
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        const dim3 grid = a.tiles ? dim3(a.n1d) : dim3(a.gx * a.gy);
+        hipLaunchKernelGGL((wall_kernel<S>), grid, dim3(a.block_x), 0, a.stream, a.views, a.tiles,
+                           a.rows, a.gx, a.parity);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
 #ifdef LB_SWEEP_UNIT
 template hipError_t sweep_fmt<LB_SWEEP_UNIT>(const SweepArgs&);
+template hipError_t wall_fmt<LB_SWEEP_UNIT>(const SweepArgs&);
 template hipError_t band_fmt<LB_SWEEP_UNIT>(bool, int, dim3, const View*, BandArgs, hipStream_t);
 #else
 #define LB_EXTERN_FMT(S)                                                                   \
     extern template hipError_t sweep_fmt<S>(const SweepArgs&);                             \
+    extern template hipError_t wall_fmt<S>(const SweepArgs&);                              \
     extern template hipError_t band_fmt<S>(bool, int, dim3, const View*, BandArgs, hipStream_t);
 LB_EXTERN_FMT(ST_F64)
 LB_EXTERN_FMT(ST_F32)
@@ -1321,6 +1364,17 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
         case ST_F32C: return sweep_fmt<ST_F32C>(a);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_walls(int storage, int block_x, const View* d_views, const Tile* d_tiles,
+                        int n_blocks_1d, int grid_x, int grid_y, int rows, int parity,
+                        hipStream_t stream) {
+    if (block_x < 1 || block_x > 256 || rows < 1) return hipErrorInvalidValue;
+    const SweepArgs a{0, block_x, false, false, false, d_views, d_tiles,
+                      n_blocks_1d, grid_x, grid_y, rows, parity, nullptr, stream};
+    if (storage == ST_F64) return wall_fmt<ST_F64>(a);
+    if (storage == ST_F32) return wall_fmt<ST_F32>(a);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_band(int storage, bool tau_phi_one, const View* d_view, int nx, int ny,
