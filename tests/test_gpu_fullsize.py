@@ -94,3 +94,30 @@ def test_full_size_sampled_windows(storage):
             err = np.abs(gw - ow).max() / scale
             say(f"  {name}: {fname} err {err:.2e} (max |value| {np.abs(ow).max():.2e})")
             assert err <= 1e-12, (name, fname, err)
+
+
+@pytest.mark.parametrize("storage,tiles", [("f64", (256, 64)), ("f32", (256, 32))])
+def test_full_size_in_place_equals_two_buffers(storage, tiles):
+    """The in-place update at full size and at the tiles the benchmark times for
+    it: bit-identical to the two-buffer path after an odd and an even number of
+    steps (both layouts), the 32-step graphs included."""
+    p, inp = wl.c4_drop()
+    say(f"case full size in place {storage}, tiles {tiles}")
+    lats = []
+    for inplace in (0, 1):
+        lat = lbm.lb_init(lbm.make_params(p, storage, inplace=inplace), inp["solid"],
+                          inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"])
+        lbm.lb_set_tuning(lat, *tiles)
+        lats.append(lat)
+    for n in (33, 32):
+        for lat in lats:
+            lbm.lb_step(lat, n)
+        a, b = (lbm.lb_read_fields(lat) for lat in lats)
+        for x, y, name in zip(a, b, ("phi", "rho", "ux", "uy")):
+            assert np.array_equal(x, y), (n, name)
+        say(f"  step {lbm.lb_get_step(lats[0])}: fields identical")
+    fa, ga = lbm.lb_read_populations(lats[0])
+    fb, gb = lbm.lb_read_populations(lats[1])
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    for lat in lats:
+        lat.close()
