@@ -143,7 +143,7 @@ typedef struct {
     int64_t step;         /* n */
 } lb_diag;
 
-/* Tile shape of the sweep: block_x columns per workgroup (64, 128 or 256) and
+/* Tile shape of the sweep: block_x columns per workgroup (64, 128, 256 or 512) and
  * rows_per_block rows walked by each workgroup (1 .. 1024). */
 typedef struct {
     int32_t block_x;

@@ -386,7 +386,8 @@ void destroy_graphs(Group& g) {
 }
 
 int check_tuning(int bx, int rows) {
-    if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "block_x must be 64, 128 or 256");
+    if (bx != 64 && bx != 128 && bx != 256 && bx != 512)
+        return fail(LB_EINVAL, "block_x must be 64, 128, 256 or 512");
     if (rows < 1 || rows > 1024) return fail(LB_EINVAL, "rows_per_block must be in 1..1024");
     return LB_OK;
 }
@@ -790,7 +791,7 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
             return rc;
         }
     }
-    const int cand_bx[] = {64, 128, 256};
+    const int cand_bx[] = {64, 128, 256, 512};
     const int cand_rows[] = {8, 16, 32, 64, 128};
     int best_bx = g.block_x, best_rows = g.rows;
     float best = 1e30f;
