@@ -57,12 +57,33 @@ def sweep_key(name):
     return (st, int(m.group(2)), int(m.group(3)), m.group(4) == "true", m.group(5) == "true")
 
 
+_BAND = re.compile(r"band_kernel<\s*(\d+)\s*,\s*(\d+)\s*,\s*(\w+)\s*>")
+
+
+def band_key(name):
+    """(in-place storage name, phase) of a band pre-pass kernel name, else None."""
+    m = _BAND.search(name)
+    if not m:
+        return None
+    return STORAGE_NAMES.get(int(m.group(1)), m.group(1)) + "ip", int(m.group(2)) - 1
+
+
+def _phase(name):
+    m = _SWEEP.search(name)
+    return int(m.group(6)) - 1 if m and m.group(6) and int(m.group(6)) > 0 else None
+
+
 def short_name(name):
     k = sweep_key(name)
     if k:
         st, coll, bx, diag, g1 = k
+        ph = _phase(name)
         return (f"sweep {st} {'MRT' if coll else 'BGK'} block {bx}"
+                f"{'' if ph is None else f' phase {ph}'}"
                 f"{' +diag' if diag else ''}{' tau_phi=1' if g1 else ''}")
+    b = band_key(name)
+    if b:
+        return f"band {b[0]} phase {b[1]}"
     return name.split("(")[0][:60]
 
 
@@ -108,17 +129,33 @@ def traffic_summary(fetch_db, write_db, copy_bytes, nodes, command):
     out = {"command": command, "source_sha256": source_hash(), "nodes": nodes,
            "copy_bytes": copy_bytes, "fetch_factor": f_fac, "write_factor": w_fac,
            "formats": {}}
+    # Per format, the kernels of one step: the plain sweep (no fused
+    # diagnostics); in place, each phase's sweep and band pre-pass, averaged
+    # over the two phases.
+    groups = collections.defaultdict(list)
     for name, vals in fetch.items():
         k = sweep_key(name)
-        if not k or k[3]:            # plain sweep launches only (no fused diagnostics)
-            continue
-        st = k[0]
-        fv = sorted(vals)[len(vals) // 2] * 1024.0 * f_fac
-        wv_list = sorted(write.get(name, [0.0]))
-        wv = wv_list[len(wv_list) // 2] * 1024.0 * w_fac
+        if k and not k[3]:
+            groups[k[0]].append(name)
+        elif band_key(name):
+            groups[band_key(name)[0]].append(name)
+
+    def med(xs):
+        xs = sorted(xs)
+        return xs[len(xs) // 2]
+
+    for st, names in groups.items():
+        kern = {}
+        for name in names:
+            kern[short_name(name)] = {
+                "dispatches": len(fetch[name]),
+                "fetch_bytes": med(fetch[name]) * 1024.0 * f_fac,
+                "write_bytes": med(write.get(name, [0.0])) * 1024.0 * w_fac}
+        per_launch = 2.0 if st.endswith("ip") else 1.0   # two phases alternate
+        fv = sum(k["fetch_bytes"] for k in kern.values()) / per_launch
+        wv = sum(k["write_bytes"] for k in kern.values()) / per_launch
         alg = BYTES_PER_LU[st] * nodes
-        out["formats"][st] = {"kernel": short_name(name), "dispatches": len(vals),
-                              "fetch_bytes": fv, "write_bytes": wv,
+        out["formats"][st] = {"kernels": kern, "fetch_bytes": fv, "write_bytes": wv,
                               "algorithmic_bytes": alg, "ratio": (fv + wv) / alg}
     return out
 
