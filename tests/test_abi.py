@@ -172,3 +172,21 @@ def test_null_handle_calls_fail_cleanly():
     assert L.lb_free(None) == 0
     assert L.lb_batch_free(None) == 0
     assert b"NULL" in L.lb_last_error() or L.lb_last_error()
+
+
+def test_size_limits():
+    """The largest lattices the layout can address are accepted, larger ones are
+    rejected before any allocation (host-side computation only)."""
+    L = lbm.load_library()
+
+    def params(nx, ny, storage="f32"):
+        p = lbm.lb_params()
+        L.lb_default_params(nx, ny, ctypes.byref(p))
+        p.storage = lbm.STORAGE[storage]
+        return p
+
+    assert lbm.lb_workspace_bytes(params(14_000_000, 3, "f64")) > 14_000_000 * 3 * 288
+    for nx, ny, st in [((1 << 24) + 1, 3, "f32"), (15_000_000, 3, "f64"), (1 << 20, (1 << 14) + 1, "f32")]:
+        with pytest.raises(lbm.LbError) as e:
+            lbm.lb_workspace_bytes(params(nx, ny, st))
+        assert e.value.code == lbm.LB_EINVAL, (nx, ny, st)

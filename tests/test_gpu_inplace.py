@@ -161,3 +161,35 @@ def test_inplace_autotune_keeps_state_and_diagnostics_agree():
     a.close()
     b.close()
 
+
+
+def _cross_channels(nx=40, ny=11):
+    """Solid everywhere except a one-node-wide row and column (periodic): every
+    fluid node has exactly two fluid neighbours, or four at the crossing."""
+    solid = np.ones((ny, nx), dtype=np.uint8)
+    solid[ny // 2, :] = 0
+    solid[:, nx // 2] = 0
+    return solid
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["no walls", "one-node channels"])
+def test_inplace_degenerate_geometries(storage, case):
+    p = wl.params(40, 11, 1.2, 0.7, "mrt")
+    inp = wl.random_fields(p, seed=41, walls=False)
+    if case != "no walls":
+        solid = _cross_channels()
+        inp = {k: (np.where(solid == 0, v, 0.0) if isinstance(v, np.ndarray) and k != "solid"
+                   else v) for k, v in inp.items()}
+        inp["solid"] = solid
+        inp["dphi"] = wl.wall_field(solid, -0.1)
+    say(f"case in place {case} {storage}")
+    a, b = pair(p, inp, storage)
+    for n in (1, 40, 3):
+        lbm.lb_step(a, n)
+        lbm.lb_step(b, n)
+        assert_same(a, b, f"{case} after +{n}")
+    a.close()
+    b.close()
+    if storage == "f64":
+        run_pair(p, inp, 100, what=f"{case} in place", inplace=1)

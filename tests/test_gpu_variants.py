@@ -147,3 +147,33 @@ def test_variants_in_a_batch_equal_solo_runs():
         assert np.array_equal(fb, fs) and np.array_equal(gb, gs), k
         solo.close()
     b.close()
+
+
+def test_lattice_node_without_walls_is_mid_link():
+    p = wl.params(48, 20, 1.2, 0.7, "mrt")
+    inp = wl.random_fields(p, seed=43, walls=False)
+    say("case lattice-node without walls")
+    a = gpu_lattice(p, inp, "f64")
+    b = gpu_lattice(dict(p, bounce=LN), inp, "f64")
+    lbm.lb_step(a, 77)
+    lbm.lb_step(b, 77)
+    fa, ga = lbm.lb_read_populations(a)
+    fb, gb = lbm.lb_read_populations(b)
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    a.close()
+    b.close()
+
+
+def test_lattice_node_one_node_channels():
+    """A one-node-wide row and column: every fluid node but the crossing has six
+    wall neighbours, so most of its populations travel through wall nodes."""
+    p = dict(wl.params(40, 11, 1.2, 0.7, "mrt"), bounce=LN)
+    inp = wl.random_fields(p, seed=41, walls=False)
+    solid = np.ones((11, 40), dtype=np.uint8)
+    solid[5, :] = 0
+    solid[:, 20] = 0
+    inp = {k: (np.where(solid == 0, v, 0.0) if isinstance(v, np.ndarray) and k != "solid" else v)
+           for k, v in inp.items()}
+    inp["solid"] = solid
+    inp["dphi"] = wl.wall_field(solid, -0.1)
+    run_pair(p, inp, 150, what="one-node channels lattice-node")
