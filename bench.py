@@ -134,6 +134,7 @@ def main():
     p, inp = wl.c4_drop()
     nx, ny = p["nx"], p["ny"]
     nodes = nx * ny
+    fluid = int((inp["solid"] == 0).sum())
     storages = [s for s in args.storages.split(",") if s]
     results = {}
     for st in storages:
@@ -151,6 +152,7 @@ def main():
         mlups = nodes / (ms_step * 1e-3) / 1e6
         gbs = BYTES_PER_LU[st] * nodes / (ms_step * 1e-3) / 1e9
         results[st] = dict(ms_per_step=ms_step, mlups=mlups, gbs=gbs,
+                           mlups_fluid=fluid / (ms_step * 1e-3) / 1e6,
                            frac=gbs / PEAK_HBM_GBS, tiles=list(tune),
                            wall_ms_per_step=wall_ms / args.steps,
                            finite=bool(d["rc"] == 0))
@@ -213,6 +215,11 @@ def main():
         cpu = cpu_baseline(p, inp, args.cpu_steps)
 
     traffic = measured_traffic()
+    # Measured ceiling of a plain streaming copy (1 GiB read + written).
+    copy_gbs = None
+    if not args.quick:
+        copy_gbs = lbm.lb_bandwidth_probe(1 << 30, 20)
+        log(f"copy probe: {copy_gbs:.0f} GB/s read + write")
 
     def traffic_gbs(st):
         if not traffic or st not in traffic:
@@ -238,13 +245,16 @@ def main():
                                f"ratio 10, D2Q9 binary free-energy LB",
                    "storage": head, "lattice": [nx, ny], "tiles": r["tiles"],
                    "gbs_algorithmic": round(r["gbs"], 1),
+                   "mlups_fluid_nodes": round(r["mlups_fluid"], 1), "fluid_nodes": fluid,
                    "speedup_vs_f64": round(r["mlups"] / results["f64"]["mlups"], 3)
                    if "f64" in results else None},
         "roofline": {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": traffic_gbs(head),
                      "traffic_ratio": (round(traffic[head]["ratio"], 4)
-                                       if traffic and head in traffic else None)},
-        "variants": {s: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
+                                       if traffic and head in traffic else None),
+                     "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1)},
+        "variants": {s: {"mlups": round(v["mlups"], 1), "mlups_fluid": round(v["mlups_fluid"], 1),
+                         "ms_per_step": round(v["ms_per_step"], 5),
                          "gbs": round(v["gbs"], 1), "frac": round(v["frac"], 4),
                          "bytes_per_lu": BYTES_PER_LU[s], "tiles": v["tiles"],
                          "traffic_gbs": traffic_gbs(s),
@@ -320,12 +330,34 @@ def cpu_baseline(p, inp, steps):
     dt = time.perf_counter() - t0
     nodes = p["nx"] * p["ny"]
     v = nodes * n / dt / 1e6
+    threads = oracle.get_threads()
     log(f"cpu oracle: {n} steps of {p['nx']}x{p['ny']} in {dt:.1f} s = {v:.2f} MLUPS "
-        f"({oracle.get_threads()} threads)")
-    return {"value": round(v, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
+        f"({threads} threads)")
+    # One thread, on a shorter sample: one further step (about 10 s).
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(1)
+    v1 = nodes / (time.perf_counter() - t0) / 1e6
+    oracle.set_threads(threads)
+    log(f"cpu oracle, 1 thread: 1 step = {v1:.3f} MLUPS")
+    return {"value": round(v, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} FP64 oracle steps of the full {p['nx']}x{p['ny']} lattice "
-                      f"after 1 untimed step"}
+                      f"after 1 untimed step",
+            "single_thread": {"value": round(v1, 4), "unit": "MLUPS", "cores": 1,
+                              "sample": "1 further step of the same lattice"},
+            "host_cpu": host_cpu()}
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
