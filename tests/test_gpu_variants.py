@@ -177,3 +177,21 @@ def test_lattice_node_one_node_channels():
     inp["solid"] = solid
     inp["dphi"] = wl.wall_field(solid, -0.1)
     run_pair(p, inp, 150, what="one-node channels lattice-node")
+
+
+def test_tau_table_compressed_formats():
+    """The table applies to every storage format: F64C against the oracle at the
+    FP64 tolerance, F32C at the reduced-precision gate."""
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(60.0, 0.04, 0.04), seed=201)
+    p = dict(p, tau_lut=10000)
+    run_pair(p, inp, 500, storage="f64c", what="C2 256x128 mrt tau table f64c")
+    say("case tau table f32c")
+    lat = gpu_lattice(p, inp, "f32c")
+    lbm.lb_step(lat, 2000)
+    orc = make_oracle(p, inp)
+    orc.step(2000)
+    fluid = inp["solid"] == 0
+    d = np.abs(lbm.lb_read_fields(lat)[0] - orc.fields()[0])[fluid].max()
+    say(f"  max|dphi| {d:.2e}")
+    assert d <= 1e-3
+    lat.close()
