@@ -358,24 +358,45 @@ __device__ inline void pull9(const Rows& R, const View& v, const ColOff& co, uin
 // 16-bit formats: the populations arriving at fluid node (x, y) that the sweep
 // takes together with phi: the paired f_i (i = 2, 4..8) into fo[i], and g into
 // go (go[0] = q of g_0, base its b). f_0, f_1, f_3 are pulled separately.
+// pairs_issue loads the words (the pair words, the G0Code of g_0, the 16-bit
+// g_1 and g_3) and pairs_decode turns them into values, taking the bounce-back
+// ones from the node itself; the sweep issues the loads one step before it
+// decodes them.
 template <int S>
-__device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
-                                  float fo[9], float go[9], float& base) {
+__device__ inline void pairs_issue(const Rows& R, const View& v, const ColOff& co,
+                                   uint32_t raw[9]) {
     using F = Fmt<S>;
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int r = EY[i] > 0 ? 1 : (EY[i] < 0 ? 2 : 0);
         constexpr int c = EX[i] > 0 ? 1 : (EX[i] < 0 ? 2 : 0);
         if constexpr (F::paired(i)) {
-            const uint32_t w = buf_ld<uint32_t>(R.r[r], co.c[c] * 2, F::template pbase<i>(v));
-            fo[i] = F::h2f((uint16_t)(w & 0xFFFFu)) * (1.0f / F::kF);
-            go[i] = F::h2f((uint16_t)(w >> 16)) * (1.0f / F::kG);
+            raw[i] = buf_ld<uint32_t>(R.r[r], co.c[c] * 2, F::template pbase<i>(v));
         } else if constexpr (i == 0) {
-            const uint32_t u = buf_ld<uint32_t>(R.r[0], co.c9, F::template poff<9>(v));
-            go[0] = G0Code::q(u);
-            base = G0Code::b(u);
+            raw[0] = buf_ld<uint32_t>(R.r[0], co.c9, F::template poff<9>(v));
         } else {
-            go[i] = ldp<S, 9 + i>(R.r[r], v, co, c);
+            using E = typename F::template E<9 + i>;
+            raw[i] = buf_ld<E>(R.r[r], co.c[c] * F::template colmul<9 + i>(),
+                               F::template poff<9 + i>(v));
+        }
+    });
+}
+
+template <int S>
+__device__ inline void pairs_decode(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
+                                    const uint32_t raw[9], float fo[9], float go[9],
+                                    float& base) {
+    using F = Fmt<S>;
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (F::paired(i)) {
+            fo[i] = F::h2f((uint16_t)(raw[i] & 0xFFFFu)) * (1.0f / F::kF);
+            go[i] = F::h2f((uint16_t)(raw[i] >> 16)) * (1.0f / F::kG);
+        } else if constexpr (i == 0) {
+            go[0] = G0Code::q(raw[0]);
+            base = G0Code::b(raw[0]);
+        } else {
+            go[i] = F::template dec<9 + i>((typename F::template E<9 + i>)raw[i]);
         }
     });
     if (nb != 0u) {
@@ -399,6 +420,14 @@ __device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co
             }
         });
     }
+}
+
+template <int S>
+__device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
+                                  float fo[9], float go[9], float& base) {
+    uint32_t raw[9];
+    pairs_issue<S>(R, v, co, raw);
+    pairs_decode<S>(R, v, co, nb, raw, fo, go, base);
 }
 
 // phi = sum of the nine g pulled at (x, y), for callers that need only phi.
@@ -698,6 +727,68 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         }
     };
 
+    // 16-bit formats: the loads of ring row y + 3d and of f_0, f_1, f_3 of row
+    // y + d are issued while row y is collided and consumed in the next step,
+    // so each row's memory latency overlaps a row of arithmetic.
+    constexpr bool kPF = F::packed;
+    uint32_t rawM[kPF ? 9 : 1], rawH[kPF ? 9 : 1];  // words of this column, of the halo column
+    uint32_t rawNbM = 0xFFu, rawNbH = 0xFFu;
+    real pf0 = 0, pf1 = 0, pf3 = 0;
+    auto raw_issue = [&](int yy) __attribute__((always_inline)) {
+        if constexpr (kPF) {
+            const int y = wrap(yy, ny);
+            const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
+            const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+            rawNbM = nrow[x];
+            if (rawNbM != 0xFFu) pairs_issue<S>(R, v, co, rawM);
+            if (halo) {
+                rawNbH = nrow[hx];
+                if (rawNbH != 0xFFu) pairs_issue<S>(R, v, hco, rawH);
+            }
+        }
+    };
+    // phi of ring row yy from the words raw_issue loaded (as fill_row forms it)
+    auto raw_finish = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
+                          real& base) __attribute__((always_inline)) {
+        if constexpr (kPF) {
+            const int y = wrap(yy, ny);
+            const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+            nb = rawNbM;
+            small = 0;
+            base = 0;
+            real ph = 0;
+            if (nb != 0xFFu) {
+                pairs_decode<S>(R, v, co, nb, rawM, fp, g, base);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) small += g[i];
+                ph = base + small;
+            }
+            sphi[yy & (kNR - 1)][t + 2] = ph;
+            if (halo) {
+                real hg[9], hf[9], hs = 0, hb = 0, hp = 0;
+                if (rawNbH != 0xFFu) {
+                    pairs_decode<S>(R, v, hco, rawNbH, rawH, hf, hg, hb);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) hs += hg[i];
+                    hp = hb + hs;
+                }
+                sphi[yy & (kNR - 1)][hcol] = hp;
+            }
+        }
+    };
+    // f_0, f_1, f_3 of row yy (pull sources as in the sweep; nbr_ its mask)
+    auto f_issue = [&](int yy, uint32_t nbr_) __attribute__((always_inline)) {
+        if constexpr (kPF) {
+            if (active && nbr_ != 0xFFu) {
+                const int y = wrap(yy, ny);
+                const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+                pf0 = ldp<S, 0>(R.r[0], v, co, 0);
+                pf1 = (nbr_ & 1u) ? ldp<S, 2>(R.r[0], v, co, 0) : ldp<S, 1>(R.r[0], v, co, 1);
+                pf3 = (nbr_ & 4u) ? ldp<S, 4>(R.r[0], v, co, 0) : ldp<S, 3>(R.r[1], v, co, 0);
+            }
+        }
+    };
+
     double d_drho = 0.0, d_phi = 0.0, d_ke = 0.0, d_umax = 0.0, d_n = 0.0;
 
     // One row: fill the ring two rows ahead in the walking direction d
@@ -705,25 +796,30 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     // the look-ahead g pulls are consumed, so both sets of loads are in flight
     // together and each row waits for memory once.
     auto step = [&](int y, real gc[9], real fc[9], uint32_t nbc, real phs, real phb,
-                    real gnew[9], real fnew[9], uint32_t& nbnew, real& snew,
-                    real& bnew) __attribute__((always_inline)) {
+                    real gnew[9], real fnew[9], uint32_t& nbnew, real& snew, real& bnew,
+                    uint32_t nbnext) __attribute__((always_inline)) {
         const bool work = active && nbc != 0xFFu;
         const uint32_t nb = nbc;
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         real f[9];
         if constexpr (F::packed) {
-            // f_2, f_4..f_8 came with the g of this row; pull f_0, f_1, f_3.
+            // f_2, f_4..f_8 came with the g of this row, f_0, f_1, f_3 were
+            // loaded in the previous step. Then ring row y + 2d from the words
+            // loaded in the previous step, and the loads for the next step.
             if (work) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) f[i] = fc[i];
-                f[0] = ldp<S, 0>(R.r[0], v, co, 0);
-                f[1] = (nb & 1u) ? ldp<S, 2>(R.r[0], v, co, 0) : ldp<S, 1>(R.r[0], v, co, 1);
-                f[3] = (nb & 4u) ? ldp<S, 4>(R.r[0], v, co, 0) : ldp<S, 3>(R.r[1], v, co, 0);
+                f[0] = pf0;
+                f[1] = pf1;
+                f[3] = pf3;
             }
+            raw_finish(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
+            f_issue(y + d, nbnext);
+            raw_issue(y + 3 * d);
         } else {
             if (work) pull9<S, 0, M>(R, v, co, pull_mask(nb), f);
+            fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         }
-        fill_row(y + 2 * d, gnew, fnew, nbnew, snew, bnew);
         __syncthreads();
         if (!work) return;
 
@@ -1069,14 +1165,16 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     if constexpr (F::gstate) __syncthreads();
     fill_row(ys + d, gB, fB, nbB, sB, bB);
     if constexpr (F::gstate) __syncthreads();
+    f_issue(ys, nbA);
+    raw_issue(ys + 2 * d);
     // Unrolled by three so the three rows of pulled values rotate roles
-    // without copies.
+    // without copies (the last argument: the mask of the next row).
     for (int k = 0; k < nrow; k += 3) {
-        step(ys + k * d, gA, fA, nbA, sA, bA, gC, fC, nbC, sC, bC);
+        step(ys + k * d, gA, fA, nbA, sA, bA, gC, fC, nbC, sC, bC, nbB);
         if (k + 1 >= nrow) break;
-        step(ys + (k + 1) * d, gB, fB, nbB, sB, bB, gA, fA, nbA, sA, bA);
+        step(ys + (k + 1) * d, gB, fB, nbB, sB, bB, gA, fA, nbA, sA, bA, nbC);
         if (k + 2 >= nrow) break;
-        step(ys + (k + 2) * d, gC, fC, nbC, sC, bC, gB, fB, nbB, sB, bB);
+        step(ys + (k + 2) * d, gC, fC, nbC, sC, bC, gB, fB, nbB, sB, bB, nbA);
     }
 
     if constexpr (DIAG) {
