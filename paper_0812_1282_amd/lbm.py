@@ -176,6 +176,7 @@ class Lattice:
 
     def __init__(self, handle, params, buffer=None, stream=None):
         self._h = handle
+        self._lib = load_library()  # held so that close() works during interpreter exit
         self.params = params
         self.shape = (params.ny, params.nx)
         self._buffer = buffer  # keeps the torch allocation alive
@@ -187,7 +188,7 @@ class Lattice:
     def close(self):
         h = getattr(self, "_h", None)
         if h:
-            load_library().lb_free(h)
+            self._lib.lb_free(h)
             self._h = None
             self._buffer = None
 
@@ -324,6 +325,7 @@ def lb_bandwidth_probe(nbytes=1 << 30, repeats=20):
 class Batch:
     def __init__(self, handle, params, keep):
         self._h = handle
+        self._lib = load_library()  # held so that close() works during interpreter exit
         self.params = params
         self._keep = keep
 
@@ -333,7 +335,7 @@ class Batch:
     def close(self):
         h = getattr(self, "_h", None)
         if h:
-            load_library().lb_batch_free(h)
+            self._lib.lb_batch_free(h)
             self._h = None
 
     def shape(self, k):
