@@ -143,7 +143,8 @@ typedef struct {
     int64_t step;         /* n */
 } lb_diag;
 
-/* Tile shape of the sweep: block_x columns per workgroup (64, 128, 256 or 512) and
+/* Tile shape of the sweep: block_x columns per workgroup (64, 128, 256, 512 or 1024;
+ * LB_F64C up to 512) and
  * rows_per_block rows walked by each workgroup (1 .. 1024). */
 typedef struct {
     int32_t block_x;

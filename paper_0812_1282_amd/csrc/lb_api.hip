@@ -386,8 +386,8 @@ void destroy_graphs(Group& g) {
 }
 
 int check_tuning(int bx, int rows) {
-    if (bx != 64 && bx != 128 && bx != 256 && bx != 512)
-        return fail(LB_EINVAL, "block_x must be 64, 128, 256 or 512");
+    if (bx != 64 && bx != 128 && bx != 256 && bx != 512 && bx != 1024)
+        return fail(LB_EINVAL, "block_x must be 64, 128, 256, 512 or 1024");
     if (rows < 1 || rows > 1024) return fail(LB_EINVAL, "rows_per_block must be in 1..1024");
     return LB_OK;
 }
@@ -755,6 +755,8 @@ int with_restored_state(Group& g, Fn fn) {
 int set_tuning(Group& g, int bx, int rows) {
     int rc = check_tuning(bx, rows);
     if (rc) return rc;
+    if (bx == 1024 && g.m[0].p.storage == LB_F64C)
+        return fail(LB_EINVAL, "LB_F64C takes block_x up to 512");
     if (g.batched) {
         const int old_bx = g.block_x, old_rows = g.rows;
         g.block_x = bx;
@@ -791,7 +793,7 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
             return rc;
         }
     }
-    const int cand_bx[] = {64, 128, 256, 512};
+    const int cand_bx[] = {64, 128, 256, 512, 1024};
     const int cand_rows[] = {8, 16, 32, 64, 128};
     int best_bx = g.block_x, best_rows = g.rows;
     float best = 1e30f;

@@ -1292,7 +1292,7 @@ __global__ __launch_bounds__(256) void band_kernel(const View* __restrict__ view
 // same step are independent. Tiles as in the sweep; each thread scans one
 // column of its tile.
 template <int S>
-__global__ __launch_bounds__(512) void wall_kernel(const View* __restrict__ views,
+__global__ __launch_bounds__(1024) void wall_kernel(const View* __restrict__ views,
                                                    const Tile* __restrict__ tiles, int rows,
                                                    int grid_x, int parity) {
     int member = 0, tx, ty;
@@ -1387,6 +1387,9 @@ static hipError_t sweep_b(const SweepArgs& a) {
         case 128: return sweep_d<S, C, 128>(a);
         case 256: return sweep_d<S, C, 256>(a);
         case 512: return sweep_d<S, C, 512>(a);
+        case 1024:  // the F64C rings in LDS do not fit 1024 columns
+            if constexpr (S != ST_F64C) return sweep_d<S, C, 1024>(a);
+            else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1468,7 +1471,7 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
 hipError_t launch_walls(int storage, int block_x, const View* d_views, const Tile* d_tiles,
                         int n_blocks_1d, int grid_x, int grid_y, int rows, int parity,
                         hipStream_t stream) {
-    if (block_x < 1 || block_x > 512 || rows < 1) return hipErrorInvalidValue;
+    if (block_x < 1 || block_x > 1024 || rows < 1) return hipErrorInvalidValue;
     const SweepArgs a{0, block_x, false, false, false, d_views, d_tiles,
                       n_blocks_1d, grid_x, grid_y, rows, parity, nullptr, stream};
     if (storage == ST_F64) return wall_fmt<ST_F64>(a);

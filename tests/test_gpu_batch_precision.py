@@ -13,6 +13,7 @@ import pytest
 from oracle import analysis
 from paper_0812_1282_amd import lbm, workloads as wl
 from tests.helpers import make_oracle
+from tests.test_gpu_parity import gpu_lattice
 
 pytestmark = pytest.mark.gpu
 
@@ -185,3 +186,36 @@ def test_ensemble_sample_against_oracle():
         assert abs(th - oca["theta"]) < 0.5
         assert dphi < 1e-3
     b.close()
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s", "f32", "f32c"])
+@pytest.mark.parametrize("nx,ny", [(67, 13), (300, 37)])
+def test_reduced_formats_independent_of_the_tile(storage, nx, ny):
+    """Every tile shape, 1024 columns included, gives the same bits (the 16-bit
+    formats issue their loads a step ahead of use)."""
+    p = wl.params(nx, ny, 1.0, 0.65, "mrt")
+    inp = wl.random_fields(p, seed=nx + ny)
+    inp["dphi"] = wl.wall_field(inp["solid"], 0.1)
+    say(f"case tiles {storage} {nx}x{ny}")
+    ref = None
+    for bx, rows in [(64, 1), (128, 7), (256, 32), (512, 9), (1024, 32), (1024, 2)]:
+        lat = gpu_lattice(p, inp, storage)
+        lbm.lb_set_tuning(lat, bx, rows)
+        lbm.lb_step(lat, 61)
+        f, g = lbm.lb_read_populations(lat)
+        if ref is None:
+            ref = (f, g)
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), (bx, rows)
+        lat.close()
+
+
+def test_f64c_rejects_1024_column_tiles():
+    p = wl.params(40, 20, 1.0, 1.0, "mrt")
+    inp = wl.random_fields(p, seed=3)
+    lat = gpu_lattice(p, inp, "f64c")
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_set_tuning(lat, 1024, 32)
+    assert e.value.code == lbm.LB_EINVAL
+    lbm.lb_set_tuning(lat, 512, 32)
+    lat.close()

@@ -96,7 +96,7 @@ def test_full_size_sampled_windows(storage):
             assert err <= 1e-12, (name, fname, err)
 
 
-@pytest.mark.parametrize("storage,tiles", [("f64", (512, 64)), ("f32", (512, 32))])
+@pytest.mark.parametrize("storage,tiles", [("f64", (1024, 32)), ("f32", (1024, 32))])
 def test_full_size_in_place_equals_two_buffers(storage, tiles):
     """The in-place update at full size and at the tiles the benchmark times for
     it: bit-identical to the two-buffer path after an odd and an even number of

@@ -82,7 +82,7 @@ def test_inplace_ragged_sizes_and_tunings(storage, nx, ny):
     ref = gpu_lattice(p, inp, storage)
     lbm.lb_step(ref, 61)
     for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (256, 32), (64, 2), (512, 9),
-                     (512, 64)]:
+                     (512, 64), (1024, 32), (1024, 3)]:
         lat = gpu_lattice(p, inp, storage, inplace=1)
         lbm.lb_set_tuning(lat, bx, rows)
         lbm.lb_step(lat, 61)
@@ -107,7 +107,7 @@ def test_inplace_scattered_solids(storage):
     inp["dphi"] = np.where(solid != 0, rng.uniform(-0.3, 0.3, solid.shape), 0.0)
     say(f"case in place scattered solids {storage}")
     a, b = pair(p, inp, storage)
-    for bx, rows in [(64, 5), (256, 32), (512, 32)]:
+    for bx, rows in [(64, 5), (256, 32), (512, 32), (1024, 32)]:
         lbm.lb_set_tuning(a, bx, rows)
         lbm.lb_set_tuning(b, bx, rows)
         lbm.lb_step(a, 151)

@@ -158,7 +158,8 @@ def test_ragged_sizes_and_tunings(nx, ny):
     orc = make_oracle(p, inp)
     orc.step(60)
     ref = None
-    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (256, 32), (512, 9), (512, 32)]:
+    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (256, 32), (512, 9), (512, 32),
+                     (1024, 5)]:
         lat = gpu_lattice(p, inp, "f64")
         lbm.lb_set_tuning(lat, bx, rows)
         lbm.lb_step(lat, 60)

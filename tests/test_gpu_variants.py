@@ -98,7 +98,7 @@ def test_lattice_node_ragged_sizes_and_tunings(nx, ny):
     orc = make_oracle(p, inp)
     orc.step(60)
     ref = None
-    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (512, 9)]:
+    for bx, rows in [(64, 1), (128, 7), (256, 1024), (64, 3), (512, 9), (1024, 4)]:
         lat = gpu_lattice(p, inp, "f64")
         lbm.lb_set_tuning(lat, bx, rows)
         lbm.lb_step(lat, 60)
