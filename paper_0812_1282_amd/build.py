@@ -26,6 +26,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+# roctx ranges (host-side markers for the profiler's marker trace)
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
+LINK = ["-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
 N_FORMATS = 6  # storage formats: one compilation unit of sweep kernels each
 
 
@@ -60,7 +63,7 @@ def build(verbose: bool = False, jobs: int = None) -> str:
                 sys.stderr.write(r.stderr)
                 raise subprocess.CalledProcessError(r.returncode, c)
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + \
-            [o for o, _ in cmds]
+            [o for o, _ in cmds] + LINK
         if verbose:
             print(" ".join(link), flush=True)
         subprocess.run(link, check=True)

@@ -8,6 +8,7 @@
 #include "lb_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -30,6 +31,16 @@ int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+// A host-side roctx range for the lifetime of a scope: a profiler run with
+// marker tracing shows each entry point, graph capture and graph replay on the
+// host timeline; without a profiler the calls return at once.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 #define HIPCHK(call)                                                                       \
     do {                                                                                   \
@@ -469,18 +480,28 @@ int group_step(Group& g, int64_t nsteps) {
     const int de = g.m[0].p.diag_every;
     auto is_diag = [&](int64_t s) { return de > 0 && s % de == 0; };
     int64_t left = nsteps;
+    // A window of kGraphSteps steps replays a captured graph when it starts at
+    // parity 0 and its checks fall where the graph has them: graph 1 checks at
+    // every window step s with s % de == 0 (only s = 0 when de >= kGraphSteps),
+    // graph 0 never. Other steps are launched one by one.
+    auto window_key = [&]() -> int {
+        if (left < kGraphSteps || g.parity != 0) return -1;
+        if (de == 0) return 0;
+        if (g.step % de == 0 && (kGraphSteps % de == 0 || de >= kGraphSteps)) return 1;
+        if (de >= kGraphSteps && g.step - g.step % de + de >= g.step + kGraphSteps) return 0;
+        return -1;
+    };
     while (left > 0) {
-        const bool graph_ok = left >= kGraphSteps && g.parity == 0 &&
-                              (de == 0 || (kGraphSteps % de == 0 && g.step % de == 0));
-        if (graph_ok) {
-            const int key = de > 0 ? 1 : 0;
+        const int key = window_key();
+        if (key >= 0) {
             if (!g.graph[key]) {
+                Range r("lb graph capture");
                 if (!g.capture_stream)
                     HIPCHK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
                 HIPCHK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
                 hipError_t ce = hipSuccess;
                 for (int s = 0; s < kGraphSteps && ce == hipSuccess; ++s)
-                    ce = enqueue_one(g, de > 0 && s % de == 0, s & 1, g.capture_stream);
+                    ce = enqueue_one(g, key == 1 && s % de == 0, s & 1, g.capture_stream);
                 hipGraph_t graph = nullptr;
                 hipError_t ee = hipStreamEndCapture(g.capture_stream, &graph);
                 if (ce != hipSuccess || ee != hipSuccess) {
@@ -493,7 +514,10 @@ int group_step(Group& g, int64_t nsteps) {
                 if (ie != hipSuccess)
                     return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
             }
-            HIPCHK(hipGraphLaunch(g.graph[key], g.stream));
+            {
+                Range r("lb graph replay");
+                HIPCHK(hipGraphLaunch(g.graph[key], g.stream));
+            }
             g.step += kGraphSteps;
             left -= kGraphSteps;
             continue;
@@ -703,6 +727,7 @@ void free_group(Group& g) {
 int init_single(const lb_params* p, const uint8_t* solid, const double* dphi, const double* phi0,
                 const double* rho0, const double* ux0, const double* uy0, void* stream, void* ext,
                 size_t ext_bytes, lb_handle** out) {
+    Range range("lb_init");
     if (!out) return fail(LB_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate_params(p);
@@ -776,14 +801,22 @@ int set_tuning(Group& g, int bx, int rows) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
+// Keyed by the current device's architecture name as well as the problem, so
+// one process driving devices of different kinds tunes each.
+std::map<std::tuple<std::string, int, int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
 
 int autotune(Group& g, int steps, lb_tuning* chosen) {
+    Range range("lb autotune");
     if (steps < 1) return fail(LB_EINVAL, "steps_per_trial must be >= 1");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
     int max_ny = 0, total = 0;
     for (auto& mb : g.m) { max_ny = std::max(max_ny, mb.p.ny); total += mb.p.nx * mb.p.ny; }
-    const auto key = std::make_tuple(g.m[0].p.nx, max_ny, g.m[0].p.storage, g.m[0].p.collision,
-                                     g.m[0].p.inplace, g.batched ? total : -1);
+    const auto key = std::make_tuple(std::string(prop.gcnArchName), g.m[0].p.nx, max_ny,
+                                     g.m[0].p.storage, g.m[0].p.collision, g.m[0].p.inplace,
+                                     g.batched ? total : -1);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -893,6 +926,7 @@ int lb_init_ext(const lb_params* p, const uint8_t* solid, const double* wall_dph
 }
 
 int lb_step(lb_handle* h, int64_t nsteps) {
+    Range r("lb_step");
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     return group_step(h->g, nsteps);
 }
@@ -1113,6 +1147,7 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
                   const double* const* wall_dphi, const double* const* phi0,
                   const double* const* rho0, const double* const* ux0, const double* const* uy0,
                   void* stream, const lb_tuning* tuning, lb_batch** out) {
+    Range range("lb_batch_init");
     if (!out) return fail(LB_EINVAL, "out is NULL");
     *out = nullptr;
     if (n < 1 || !params || !solid || !phi0) return fail(LB_EINVAL, "need n >= 1, params, solid, phi0");
@@ -1211,6 +1246,7 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
 }
 
 int lb_batch_step(lb_batch* b, int64_t nsteps) {
+    Range r("lb_batch_step");
     if (!b) return fail(LB_EINVAL, "batch is NULL");
     return group_step(b->g, nsteps);
 }

@@ -4,17 +4,22 @@
     python -m paper_0812_1282_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes N \
         --nodes N --command CMD --out FILE.json
     python -m paper_0812_1282_amd.profiling counters DB [DB ...] --command CMD --out FILE.md
+    python -m paper_0812_1282_amd.profiling markers DB --command CMD --out FILE.md
 
 `trace` tabulates a --kernel-trace database: calls, total, average and median
 duration per kernel. `counters` tabulates the median per dispatch of every
-counter in --pmc databases for the plain sweep launches of each format. `traffic` turns two --pmc databases (FETCH_SIZE, then
+counter in --pmc databases for the plain sweep launches of each format.
+`markers` tabulates the library's roctx ranges from a --marker-trace database
+(host time per entry point, graph capture and graph replay). `traffic` turns
+two --pmc databases (FETCH_SIZE, then
 WRITE_SIZE, in KiB per dispatch) into HBM bytes per sweep launch, each counter
 scaled so that the device copy of a known size that the profiled command runs
 first (bench.py --copy-calibration-mib) reads and writes exactly its size. The
 JSON records a hash of the kernel sources, and bench.py reports the traffic
 only while the sources still hash the same.
 
-Reads only the SQLite output of rocprofv3 (tables `kernels`, `pmc_events`).
+Reads only the SQLite output of rocprofv3 (tables `kernels`, `pmc_events`,
+`regions`).
 """
 import argparse
 import collections
@@ -181,6 +186,26 @@ def counters_summary(dbs, command):
     return "\n".join(lines) + "\n"
 
 
+def marker_summary(db, command):
+    """Calls, total, average and median host duration of each roctx range."""
+    c = sqlite3.connect(db).cursor()
+    agg = collections.defaultdict(list)
+    for extdata, d in c.execute("select extdata, duration from regions"):
+        try:
+            name = json.loads(extdata).get("message", "?")
+        except (TypeError, ValueError):
+            name = str(extdata)
+        agg[name].append(float(d))
+    lines = ["# rocprofv3 marker trace (library roctx ranges, host time)", "",
+             f"Command: `{command}`", "",
+             "| range | calls | total ms | avg us | median us |", "|---|---|---|---|---|"]
+    for name, ds in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        ds = sorted(ds)
+        lines.append(f"| {name} | {len(ds)} | {sum(ds) / 1e6:.3f} | "
+                     f"{sum(ds) / len(ds) / 1e3:.2f} | {ds[len(ds) // 2] / 1e3:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -199,9 +224,15 @@ def main(argv=None):
     c.add_argument("dbs", nargs="+")
     c.add_argument("--command", required=True)
     c.add_argument("--out", required=True)
+    m = sub.add_parser("markers")
+    m.add_argument("db")
+    m.add_argument("--command", required=True)
+    m.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         text = trace_summary(a.db, a.command)
+    elif a.cmd == "markers":
+        text = marker_summary(a.db, a.command)
     elif a.cmd == "counters":
         text = counters_summary(a.dbs, a.command)
     else:

@@ -267,13 +267,37 @@ def test_determinism_graph_and_memory_paths():
         assert np.array_equal(r[0], runs[0][0]) and np.array_equal(r[1], runs[0][1])
 
 
-def test_periodic_check_reports_nonfinite_state():
+@pytest.mark.parametrize("inplace", [0, 1])
+@pytest.mark.parametrize("every", [8, 48, 100])
+def test_graph_windows_with_periodic_checks(every, inplace):
+    """With a check every 8 steps the 32-step graph carries four checks; with 48
+    or 100 a window replays the graph with one check at its start or the one
+    with none, and steps near a check are launched singly. All of it equals
+    single-step calls, and the diagnostics agree."""
+    p, inp = wl.c2_drop("mrt", analysis.theory_dphi(70.0, 0.04, 0.04))
+    say(f"case graph windows, check every {every}, inplace {inplace}")
+    out = []
+    for chunks in ([3, 300, 1, 97], [1] * 401):
+        params = lbm.make_params(p, "f64", diag_every=every, inplace=inplace)
+        lat = lbm.lb_init(params, inp["solid"], inp["phi0"], dphi=inp["dphi"], rho0=inp["rho0"])
+        for c in chunks:
+            lbm.lb_step(lat, c)
+        out.append((lbm.lb_read_populations(lat), lbm.lb_diagnostics(lat)))
+        lat.close()
+    (a, da), (b, db) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert da == db
+
+
+@pytest.mark.parametrize("every", [10, 100])
+def test_periodic_check_reports_nonfinite_state(every):
     """diag_every > 0 enqueues the conservation sums; a run driven unstable (tau
-    close to 1/2 and a large velocity) is reported as LB_ENUMERIC."""
+    close to 1/2 and a large velocity) is reported as LB_ENUMERIC, also when the
+    checks sit inside replayed 32-step graphs (every = 100)."""
     p = wl.params(64, 16, 0.5001, 0.5001, "bgk")
     inp = wl.random_fields(p, seed=2, amp_u=0.4)
-    say("case unstable run with periodic check")
-    lat = lbm.lb_init(lbm.make_params(p, "f64", diag_every=10), inp["solid"], inp["phi0"],
+    say(f"case unstable run with periodic check every {every}")
+    lat = lbm.lb_init(lbm.make_params(p, "f64", diag_every=every), inp["solid"], inp["phi0"],
                       dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
     lbm.lb_step(lat, 2000)
     with pytest.raises(lbm.LbError) as e:
