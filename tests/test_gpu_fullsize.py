@@ -61,6 +61,16 @@ def test_full_size_sampled_windows(storage):
     assert abs(d1["sum_phi"] - d0["sum_phi"]) <= 1e-12 * d0["n_fluid"]
     fields = lbm.lb_read_fields(lat)
     lat.close()
+    compare_windows(p, inp, fields, 1e-12)
+
+
+def compare_windows(p, inp, fields, tol):
+    """Every field of the full-lattice run against the oracle on four windows
+    (contact line, drop apex, periodic seam, top wall): phi and rho relative to
+    their scale, u absolutely (lattice units; u is a difference of O(0.1)
+    populations). Returns the largest error of each field."""
+    nx, ny = p["nx"], p["ny"]
+    worst = {}
     cases = [
         ("contact line, bottom wall", nx // 2 + 800 - W // 2, 0, False, True),
         ("drop apex", nx // 2 - W // 2, 800 - W // 2, False, False),
@@ -88,12 +98,37 @@ def test_full_size_sampled_windows(storage):
         for fname, g, o in zip(("phi", "rho", "ux", "uy"), fields, ofields):
             gw = g[np.ix_(ys, xs)]
             ow = o[r0:r1, c0:c1]
-            # phi and rho relative to their scale; u absolutely (lattice units),
-            # as u is a difference of O(0.1) populations.
             scale = max(np.abs(ow).max(), 1e-300) if fname in ("phi", "rho") else 1.0
             err = np.abs(gw - ow).max() / scale
+            worst[fname] = max(worst.get(fname, 0.0), err)
             say(f"  {name}: {fname} err {err:.2e} (max |value| {np.abs(ow).max():.2e})")
-            assert err <= 1e-12, (name, fname, err)
+            assert err <= tol, (name, fname, err)
+    return worst
+
+
+# Reduced-precision formats at the tiles the benchmark times. Each stored
+# population (or stored phi, Gamma mu, u of the compressed-g formats) carries a
+# relative rounding error of at most 2^-24 (FP32), 2^-11 (FP16) or 2^-8 (BF16);
+# a node's phi, rho and u sum nine such values, and over 10 steps the
+# collision relaxes rather than amplifies them. The bounds: 1e-5 for FP32
+# storage, 1e-3 for FP16 (the benchmark's accuracy gate on phi) and 1e-2 for
+# BF16.
+REDUCED = [("f32", (512, 32), 1e-5), ("f32c", (512, 32), 1e-5), ("f16s", (1024, 32), 1e-3),
+           ("bf16s", (512, 32), 1e-2)]
+
+
+@pytest.mark.parametrize("storage,tiles,tol", REDUCED)
+def test_full_size_reduced_formats_sampled_windows(storage, tiles, tol):
+    p, inp = wl.c4_drop()
+    say(f"case full size {p['nx']}x{p['ny']} {storage}, {K} steps, tiles {tiles}")
+    lat = lbm.lb_init(lbm.make_params(p, storage), inp["solid"], inp["phi0"], dphi=inp["dphi"],
+                      rho0=inp["rho0"])
+    lbm.lb_set_tuning(lat, *tiles)
+    lbm.lb_step(lat, K)
+    fields = lbm.lb_read_fields(lat)
+    lat.close()
+    worst = compare_windows(p, inp, fields, tol)
+    say(f"  worst {storage}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()))
 
 
 @pytest.mark.parametrize("storage,tiles", [("f64", (1024, 32)), ("f32", (1024, 32))])
