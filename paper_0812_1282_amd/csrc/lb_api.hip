@@ -831,11 +831,20 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     int best_bx = g.block_x, best_rows = g.rows;
     float best = 1e30f;
     const int diag_save = g.m[0].p.diag_every;
+    // Destroys the timing events on every return path of the trial loop.
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    };
     int rc = with_restored_state(g, [&]() -> int {
         for (auto& mb : g.m) mb.p.diag_every = 0;
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
+        Events ev;
+        HIPCHK(hipEventCreate(&ev.e0));
+        HIPCHK(hipEventCreate(&ev.e1));
+        hipEvent_t e0 = ev.e0, e1 = ev.e1;
         for (int bx : cand_bx)
             for (int rows : cand_rows) {
                 if (rows > 2 * max_ny) continue;
@@ -851,8 +860,6 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
                 if (ms < best) { best = ms; best_bx = bx; best_rows = rows; }
             }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         return LB_OK;
     });
     for (auto& mb : g.m) mb.p.diag_every = diag_save;
@@ -865,6 +872,17 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     }
     if (chosen) *chosen = lb_tuning{g.block_x, g.rows};
     return LB_OK;
+}
+
+// Parameters that define the computation, compared field by field (a struct
+// compare would also compare padding bytes); diag_every may differ.
+bool same_params(const lb_params& a, const lb_params& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.A == b.A && a.B == b.B && a.kappa == b.kappa &&
+           a.Gamma == b.Gamma && a.tau_alpha == b.tau_alpha && a.tau_beta == b.tau_beta &&
+           a.tau_phi == b.tau_phi && a.rho_ref == b.rho_ref && a.collision == b.collision &&
+           a.storage == b.storage && a.zero_u_feq == b.zero_u_feq &&
+           a.zero_u_geq == b.zero_u_geq && a.tau_clamp == b.tau_clamp &&
+           a.inplace == b.inplace && a.tau_lut == b.tau_lut && a.bounce == b.bounce;
 }
 
 struct CkptHeader {
@@ -1045,9 +1063,7 @@ int lb_load(lb_handle* h, const char* path) {
     }
     std::fclose(fp);
     if (!ok) return fail(LB_EIO, std::string("not a matching checkpoint: ") + path);
-    lb_params a = hd.params, b = mb.p;
-    a.diag_every = b.diag_every = 0;
-    if (std::memcmp(&a, &b, sizeof(lb_params)) != 0 || solid != mb.solid)
+    if (!same_params(hd.params, mb.p) || solid != mb.solid)
         return fail(LB_EINVAL, "checkpoint parameters or mask differ from the handle");
     HIPCHK(hipStreamSynchronize(g.stream));
     HIPCHK(hipMemcpy(mb.view.buf[0], buf.data(), buf.size(), hipMemcpyHostToDevice));

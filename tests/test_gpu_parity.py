@@ -250,6 +250,41 @@ def test_checkpoint_resume_is_bitwise(tmp_path):
     c.close()
 
 
+def test_checkpoint_rejects_other_cases(tmp_path):
+    """A checkpoint loads into a handle of the same case whatever its check
+    cadence, and is refused by one whose parameters or mask differ."""
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    say("case checkpoint matching")
+    a = gpu_lattice(p, inp, "f64")
+    lbm.lb_step(a, 7)
+    path = tmp_path / "state.ckpt"
+    lbm.lb_save(a, path)
+    ok = lbm.lb_init(lbm.make_params(p, "f64", diag_every=5), inp["solid"], inp["phi0"],
+                     dphi=inp["dphi"], rho0=inp["rho0"])
+    lbm.lb_load(ok, path)
+    assert lbm.lb_get_step(ok) == 7
+    fa, ga = lbm.lb_read_populations(a)
+    fb, gb = lbm.lb_read_populations(ok)
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    ok.close()
+    other = gpu_lattice(dict(p, tau_beta=0.9), inp, "f64")
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_load(other, path)
+    assert e.value.code == lbm.LB_EINVAL
+    other.close()
+    solid = inp["solid"].copy()
+    solid[10, 3] = 1
+    moved = dict(inp, solid=solid)
+    for k in ("phi0", "rho0"):
+        moved[k] = np.where(solid != 0, 0.0, inp[k])
+    other = gpu_lattice(p, moved, "f64")
+    with pytest.raises(lbm.LbError) as e:
+        lbm.lb_load(other, path)
+    assert e.value.code == lbm.LB_EINVAL
+    other.close()
+    a.close()
+
+
 def test_determinism_graph_and_memory_paths():
     """Two runs are bitwise equal; the captured-graph path (>= 32 steps per call)
     equals single-step calls; library-allocated and torch-allocated memory agree."""
