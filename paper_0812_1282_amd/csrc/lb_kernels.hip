@@ -174,12 +174,19 @@ struct Fmt16 {
         if constexpr (S == ST_F16S) return __builtin_bit_cast(uint16_t, (_Float16)x);
         else return float_to_bf16(x);
     }
+    // A stored element times inv = 2^-k, exact. Written as fma(h, inv, +0) so
+    // that FP16 widens and scales in one mixed-precision FMA instead of a
+    // convert and a multiply; the only difference from h * inv is that a -0
+    // element comes out as +0.
+    __device__ static float unscale(uint16_t h, float inv) {
+        return __builtin_fmaf(h2f(h), inv, 0.0f);
+    }
     template <int p>
     __device__ static real dec(E<p> x) {
         static_assert(p != 9, "g_0 goes through G0Code");
         if constexpr (wide(p)) return x;
-        else if constexpr (p < 9) return h2f(x) * (1.0f / kF);
-        else return h2f(x) * (1.0f / kG);
+        else if constexpr (p < 9) return unscale(x, 1.0f / kF);
+        else return unscale(x, 1.0f / kG);
     }
     template <int p>
     __device__ static E<p> enc(real x) {
@@ -390,8 +397,8 @@ __device__ inline void pairs_decode(const Rows& R, const View& v, const ColOff& 
     static_for<9>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         if constexpr (F::paired(i)) {
-            fo[i] = F::h2f((uint16_t)(raw[i] & 0xFFFFu)) * (1.0f / F::kF);
-            go[i] = F::h2f((uint16_t)(raw[i] >> 16)) * (1.0f / F::kG);
+            fo[i] = F::unscale((uint16_t)(raw[i] & 0xFFFFu), 1.0f / F::kF);
+            go[i] = F::unscale((uint16_t)(raw[i] >> 16), 1.0f / F::kG);
         } else if constexpr (i == 0) {
             go[0] = G0Code::q(raw[0]);
             base = G0Code::b(raw[0]);
@@ -408,8 +415,8 @@ __device__ inline void pairs_decode(const Rows& R, const View& v, const ColOff& 
                     if constexpr (F::paired(i) && F::paired(OPP[i])) {
                         const uint32_t w =
                             buf_ld<uint32_t>(R.r[0], co.c[0] * 2, F::template pbase<OPP[i]>(v));
-                        fo[i] = F::h2f((uint16_t)(w & 0xFFFFu)) * (1.0f / F::kF);
-                        go[i] = F::h2f((uint16_t)(w >> 16)) * (1.0f / F::kG);
+                        fo[i] = F::unscale((uint16_t)(w & 0xFFFFu), 1.0f / F::kF);
+                        go[i] = F::unscale((uint16_t)(w >> 16), 1.0f / F::kG);
                     } else if constexpr (F::paired(i)) {
                         fo[i] = ldp<S, OPP[i]>(R.r[0], v, co, 0);
                         go[i] = ldp<S, 9 + OPP[i]>(R.r[0], v, co, 0);
@@ -1062,7 +1069,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 constexpr int i = decltype(ic)::value;
                 if constexpr (F::paired(i)) {
                     hf[i] = F::f2h(fo[i] * F::kF);
-                    r[i] = F::h2f((uint16_t)hf[i]) * (1.0f / F::kF);
+                    r[i] = F::unscale((uint16_t)hf[i], 1.0f / F::kF);
                 }
                 if constexpr (i > 0) {
                     const real gi = G1 ? geq[i] : gc[i] - itp * (gc[i] - geq[i]);
