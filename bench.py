@@ -114,8 +114,8 @@ def time_steps(torch, lbm, lat, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs "
-              "are not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sweep has "
+              "no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_0812_1282_amd import lbm, workloads as wl
