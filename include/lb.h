@@ -36,6 +36,11 @@
  * never throws; lb_last_error() returns the calling thread's last message.
  * Host arrays passed in are borrowed for the duration of the call only.
  * Asynchronous device failures surface at the next synchronising call.
+ *
+ * Profiling: lb_init, lb_step, lb_batch_init, lb_batch_step, the autotuner,
+ * graph capture and graph replay each open a roctx range (host time), seen
+ * by a profiler's marker trace; without a profiler they cost nothing
+ * measurable.
  */
 #ifndef LB_H
 #define LB_H
