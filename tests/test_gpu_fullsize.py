@@ -156,3 +156,62 @@ def test_full_size_in_place_equals_two_buffers(storage, tiles):
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
     for lat in lats:
         lat.close()
+
+
+# The widest lattice the library accepts: a row block of the FP64 layout (18
+# planes of the padded width, 8 bytes each) must stay under 2^31 bytes, so that
+# every in-row byte offset fits the 32-bit offsets of the buffer accesses.
+NX_MAX = ((1 << 31) - 1) // (18 * 8) // 64 * 64
+
+
+def _widest_case(ny=6):
+    """NX_MAX x ny, walls in the first and last rows, phi varying on scales of
+    13-40 nodes along x (so the x pulls and the stencil carry real differences
+    all along the row), a small density and velocity pattern."""
+    nx = NX_MAX
+    p = wl.params(nx, ny, 1.2, 0.8, "mrt")
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    fluid = solid == 0
+    phi0 = np.tanh(1.5 * (np.sin(2 * np.pi * x / 40 + 0.7 * y) + 0.3 * np.sin(2 * np.pi * x / 13)))
+    phi0 = np.where(fluid, phi0, 0.0)
+    rho0 = np.where(fluid, 1.0 + 0.01 * np.sin(2 * np.pi * x / 29), 0.0)
+    ux0 = np.where(fluid, 0.01 * np.cos(2 * np.pi * x / 31), 0.0)
+    uy0 = np.zeros((ny, nx))
+    dphi = np.where(solid != 0, 0.05, 0.0)
+    return p, {"solid": solid, "dphi": dphi, "phi0": phi0, "rho0": rho0, "ux0": ux0, "uy0": uy0}
+
+
+@pytest.mark.parametrize("storage,inplace,tiles,tol", [("f64", 0, (512, 32), 1e-12),
+                                                       ("f64", 1, (1024, 32), 1e-12),
+                                                       ("f16s", 0, (1024, 32), 1e-3)])
+def test_widest_lattice_against_oracle(storage, inplace, tiles, tol):
+    """At the largest accepted width (the last tile ragged at 1024 columns),
+    windows at the row start (across the periodic seam), the middle and the row
+    end, whole in y, against the oracle."""
+    p, inp = _widest_case()
+    nx, ny = p["nx"], p["ny"]
+    say(f"case widest lattice {nx}x{ny} {storage} inplace={inplace} tiles {tiles}")
+    lat = lbm.lb_init(lbm.make_params(p, storage, inplace=inplace), inp["solid"], inp["phi0"],
+                      dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+    lbm.lb_set_tuning(lat, *tiles)
+    lbm.lb_step(lat, K)
+    fields = lbm.lb_read_fields(lat)
+    lat.close()
+    say("  GPU run done")
+    for x0 in (nx - W // 2, nx // 2, nx - W):
+        xs = np.arange(x0, x0 + W) % nx
+        sub = {k: v[:, xs].copy() for k, v in inp.items()}
+        wp = dict(p, nx=W)
+        orc = make_oracle(wp, sub)
+        orc.step(K)
+        for fname, g, o in zip(("phi", "rho", "ux", "uy"), fields, orc.fields()):
+            gw = g[:, xs[MARGIN:W - MARGIN]]
+            ow = o[:, MARGIN:W - MARGIN]
+            scale = max(np.abs(ow).max(), 1e-300) if fname in ("phi", "rho") else 1.0
+            err = np.abs(gw - ow).max() / scale
+            say(f"  window at x = {x0}: {fname} err {err:.2e}")
+            assert err <= tol, (x0, fname, err)
