@@ -43,12 +43,8 @@ __device__ constexpr int OPP[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
 // ------------------------------------------------------------------ storage
 
 __device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ inline uint16_t float_to_bf16(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even; gfx950 converts in one instruction (v_cvt_pk_bf16_f32).
+__device__ inline uint16_t float_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 // Storage format traits. Plane p: 0..8 = f_0..f_8, 9..17 = g_0..g_8.
 //   E<p>    element type of plane p
