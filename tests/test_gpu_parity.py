@@ -225,6 +225,29 @@ def test_contact_angle_matches_oracle_measurement():
     lat.close()
 
 
+def test_mrt_at_unit_rates_is_bgk_tau_one():
+    """Sec. III.B: with tau = 1 in both phases every non-conserved MRT rate is 1,
+    so MRT and BGK both relax f to f^eq in one step, Step 2 off (with Step 2 on
+    they differ by design: MRT keeps the momentum of f at boundary nodes, BGK
+    takes that of f^eq, which is zero there). A check of the GPU path against
+    itself, independent of the oracle: the two operators take different
+    arithmetic, so they agree to rounding."""
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    say("case MRT at unit rates vs BGK tau = 1")
+    a = gpu_lattice(dict(p, collision="bgk"), inp, "f64", zero_u_feq=0)
+    b = gpu_lattice(dict(p, collision="mrt"), inp, "f64", zero_u_feq=0)
+    lbm.lb_step(a, 300)
+    lbm.lb_step(b, 300)
+    fa, ga = lbm.lb_read_populations(a)
+    fb, gb = lbm.lb_read_populations(b)
+    df = np.abs(fa - fb).max() / np.abs(fa).max()
+    dg = np.abs(ga - gb).max() / np.abs(ga).max()
+    say(f"  max rel diff f {df:.2e}, g {dg:.2e}")
+    assert df <= 1e-13 and dg <= 1e-13
+    a.close()
+    b.close()
+
+
 def test_checkpoint_resume_is_bitwise(tmp_path):
     p, inp = wl.c2_drop("mrt", analysis.theory_dphi(110.0, 0.04, 0.04))
     say("case checkpoint")
