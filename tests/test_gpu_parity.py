@@ -248,6 +248,40 @@ def test_mrt_at_unit_rates_is_bgk_tau_one():
     b.close()
 
 
+UNIFORM_TOL = {"f64": 1e-13, "f64c": 1e-13, "f32": 1e-6, "f32c": 1e-6, "f16s": 1e-3, "bf16s": 1e-3}
+
+
+@pytest.mark.parametrize("storage", list(UNIFORM_TOL))
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("case", ["uniform flow, periodic", "rest between walls"])
+def test_uniform_states_are_fixed_points(storage, collision, case):
+    """A uniform state is a fixed point of the method: all gradients vanish, the
+    equilibria carry exactly the state's rho, j and phi (Appendix A), streaming
+    moves equal values, and at rest bounce-back returns what it receives while
+    the wetting ghosts (wall gradient 0) repeat the uniform phi. phi = 0.3 keeps
+    mu and the g^eq terms nonzero. A check of the GPU path alone: the fields must
+    stay at their initial values to the storage format's rounding (the stored
+    values re-encode to themselves after the first step)."""
+    nx, ny = 64, 32
+    walls = case != "uniform flow, periodic"
+    p = wl.params(nx, ny, 1.3, 0.7, collision, tau_phi=1.0 if storage.endswith("c") else 0.8)
+    solid = wl.walls_mask(nx, ny) if walls else np.zeros((ny, nx), dtype=np.uint8)
+    fluid = solid == 0
+    u0 = (0.0, 0.0) if walls else (0.04, -0.03)
+    inp = {"solid": solid, "dphi": np.zeros((ny, nx)), "phi0": np.where(fluid, 0.3, 0.0),
+           "rho0": np.where(fluid, 1.0, 0.0), "ux0": np.where(fluid, u0[0], 0.0),
+           "uy0": np.where(fluid, u0[1], 0.0)}
+    say(f"case uniform state {case} {storage} {collision}")
+    lat = gpu_lattice(p, inp, storage, zero_u_feq=0)
+    lbm.lb_step(lat, 200)
+    phi, rho, ux, uy = lbm.lb_read_fields(lat)
+    lat.close()
+    err = max(np.abs(phi - 0.3)[fluid].max(), np.abs(rho - 1.0)[fluid].max(),
+              np.abs(ux - u0[0])[fluid].max(), np.abs(uy - u0[1])[fluid].max())
+    say(f"  max deviation {err:.2e}")
+    assert err <= UNIFORM_TOL[storage], err
+
+
 def test_checkpoint_resume_is_bitwise(tmp_path):
     p, inp = wl.c2_drop("mrt", analysis.theory_dphi(110.0, 0.04, 0.04))
     say("case checkpoint")
