@@ -248,6 +248,37 @@ def test_mrt_at_unit_rates_is_bgk_tau_one():
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("phase", [1.0, -1.0])
+def test_shear_wave_viscosity_on_gpu(storage, collision, phase):
+    """A shear wave u_x = U sin(k y) in one bulk phase decays at nu k^2 with
+    nu = (tau - 1/2)/3, tau = tau_alpha in the phi = +1 phase and tau_beta in
+    the phi = -1 phase (Eqs. (tau), (kine); MRT through its stress modes). A
+    check of the GPU path alone, in the headline format too."""
+    nx, ny = 8, 48
+    ta, tb = 1.3, 0.7
+    p = wl.params(nx, ny, ta, tb, collision)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    inp = {"solid": np.zeros((ny, nx), np.uint8), "dphi": None,
+           "phi0": np.full((ny, nx), phase), "rho0": np.ones((ny, nx)),
+           "ux0": 1e-2 * np.sin(2 * np.pi * y / ny), "uy0": np.zeros((ny, nx))}
+    say(f"case shear wave {storage} {collision} phi={phase}")
+    lat = gpu_lattice(p, inp, storage, zero_u_feq=0)
+    ts, amps = [], []
+    for k in range(20):
+        lbm.lb_step(lat, 50)
+        ux = lbm.lb_read_fields(lat)[2]
+        amps.append((ux[:, 0] * np.sin(2 * np.pi * np.arange(ny) / ny)).sum() * 2 / ny)
+        ts.append((k + 1) * 50)
+    lat.close()
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    nu = ((ta if phase > 0 else tb) - 0.5) / 3
+    ratio = rate / (nu * (2 * np.pi / ny) ** 2)
+    say(f"  decay rate / (nu k^2) = {ratio:.4f}")
+    assert ratio == pytest.approx(1.0, abs=0.02)
+
+
 UNIFORM_TOL = {"f64": 1e-13, "f64c": 1e-13, "f32": 1e-6, "f32c": 1e-6, "f16s": 1e-3, "bf16s": 1e-3}
 
 
