@@ -279,6 +279,33 @@ def test_shear_wave_viscosity_on_gpu(storage, collision, phase):
     assert ratio == pytest.approx(1.0, abs=0.02)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
+def test_laplace_pressure_on_gpu(storage):
+    """Free drops of radius 8, 12, 16 in a periodic 64 x 64 box: p0 inside minus
+    outside against 1/R has the slope of the discrete flat interface's tension
+    (Eq. (pressten); Sec. II gives sqrt(8 kappa a / 9) for the continuum),
+    from GPU runs alone; the radius is fitted to the phi = 0 crossings."""
+    from tests.test_oracle_physics import _discrete_surface_tension
+    gam = _discrete_surface_tension()
+    pts = []
+    for R in (8.0, 12.0, 16.0):
+        p = wl.params(64, 64, 1.0, 1.0, "bgk", Gamma=1.0)
+        inp = wl.free_drop(p, R, seed=7)
+        say(f"case Laplace {storage} R={R}")
+        lat = gpu_lattice(p, inp, storage)
+        lbm.lb_step(lat, 3000)
+        phi, rho, ux, uy = lbm.lb_read_fields(lat)
+        lat.close()
+        p0 = rho / 3 + p["A"] * phi ** 2 / 2 + 3 * p["B"] * phi ** 4 / 4
+        xs, ys = analysis.crossing_points(phi, inp["solid"], 0, 64, 0, 64)[0].T
+        _, _, Rf = analysis.fit_circle(np.stack([xs, ys], 1))
+        pts.append((1.0 / Rf, p0[32, 32] - p0[0, 0]))
+    pts = np.array(pts)
+    slope = np.polyfit(pts[:, 0], pts[:, 1], 1)[0]
+    say(f"  slope {slope:.5f}, discrete tension {gam:.5f}")
+    assert slope == pytest.approx(gam, rel=0.03)
+
+
 UNIFORM_TOL = {"f64": 1e-13, "f64c": 1e-13, "f32": 1e-6, "f32c": 1e-6, "f16s": 1e-3, "bf16s": 1e-3}
 
 
