@@ -306,6 +306,37 @@ def test_laplace_pressure_on_gpu(storage):
     assert slope == pytest.approx(gam, rel=0.03)
 
 
+_BGK60 = pytest.mark.xfail(strict=True, reason=(
+    "measured 56.6 degrees, converged (the same to 0.1 degree from 3e4 to 2.4e5 "
+    "steps, for either fit window): with the wetting ghost rule the wall wets "
+    "3.4 degrees more than Eq. (theory) here, 0.4 degree beyond the 3-degree "
+    "reading of good agreement; reported, not re-tuned"))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
+@pytest.mark.parametrize("collision,theta", [
+    pytest.param("bgk", 60.0, marks=_BGK60), ("mrt", 60.0), ("bgk", 90.0), ("mrt", 90.0),
+    ("bgk", 120.0), ("mrt", 120.0)])
+def test_equilibrium_angle_follows_theory_on_gpu(storage, collision, theta):
+    """Fig. 2(a) set-up, equal viscosities (tau = 1), Gamma = 0.5: a semicircle of
+    radius 35 on the wall of a 300 x 100 box, 3e4 steps at the wall gradient
+    Eq. (theory) gives for theta; the fitted angle (the library's measurement)
+    is within 3 degrees of theta, the agreement the paper reports as good.
+    The wall gradient comes from the test's own copy of Eq. (theory). Measured
+    (FP64 = FP16S to 0.01 degree): BGK 56.6, 89.4, 122.4; MRT 57.1, 89.5,
+    122.2."""
+    p = wl.params(300, 100, 1.0, 1.0, collision, Gamma=0.5)
+    inp = wl.drop_on_wall(p, 35.0, 150.0, 0.0, seed=3,
+                          dphi_wall=analysis.theory_dphi(theta, 0.04, 0.04))
+    say(f"case equilibrium angle {storage} {collision} {theta}")
+    lat = gpu_lattice(p, inp, storage)
+    lbm.lb_step(lat, 30000)
+    got = lbm.lb_contact_angle(lat, 0.0, 300.0, 3.5, 90.0, 0.5, 1)["theta"]
+    lat.close()
+    say(f"  theta {got:.2f} (target {theta})")
+    assert abs(got - theta) <= 3.0
+
+
 UNIFORM_TOL = {"f64": 1e-13, "f64c": 1e-13, "f32": 1e-6, "f32c": 1e-6, "f16s": 1e-3, "bf16s": 1e-3}
 
 
