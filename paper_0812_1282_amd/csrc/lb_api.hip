@@ -351,16 +351,21 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
         stage[3 * n + h] = uy0 ? uy0[h] : 0.0;
     }
     if (p->inplace) {
-        // phi0 in the band plane; rho0, ux0, uy0 in each node's own slots of
-        // planes 1..3 (FP64) or, as low and high words, 1..6 (FP32).
-        HIPCHK(hipMemcpyAsync(v.band, stage.data(), n * 8, hipMemcpyHostToDevice, st));
+        // rho0, ux0, uy0 go to each node's own slots of planes 1..3 (FP64) or,
+        // as low and high words, 1..6 (FP32); phi0 then stays in the band
+        // plane. Each field crosses to the device as one contiguous copy into
+        // the band plane and is spread over the slots by a device-to-device 2D
+        // copy: a 2D copy from pageable host memory would move the short rows
+        // one by one.
+        char* band = reinterpret_cast<char*>(v.band);
         std::vector<uint32_t> words;
         for (int q = 0; q < 3; ++q) {
             const double* src = stage.data() + (size_t)(q + 1) * n;
             if (p->storage == LB_F64) {
-                HIPCHK(hipMemcpy2DAsync(v.buf[0] + (size_t)(1 + q) * L.pitch * 8, L.row_bytes, src,
+                HIPCHK(hipMemcpyAsync(band, src, n * 8, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpy2DAsync(v.buf[0] + (size_t)(1 + q) * L.pitch * 8, L.row_bytes, band,
                                         (size_t)nx * 8, (size_t)nx * 8, (size_t)ny,
-                                        hipMemcpyHostToDevice, st));
+                                        hipMemcpyDeviceToDevice, st));
             } else {
                 words.resize(2 * n);
                 for (size_t h = 0; h < n; ++h) {
@@ -369,13 +374,15 @@ int init_member(Member& mb, const lb_params* p, const uint8_t* solid, const doub
                     words[h] = (uint32_t)u;
                     words[n + h] = (uint32_t)(u >> 32);
                 }
+                HIPCHK(hipMemcpyAsync(band, words.data(), 2 * n * 4, hipMemcpyHostToDevice, st));
                 for (int half = 0; half < 2; ++half)
                     HIPCHK(hipMemcpy2DAsync(v.buf[0] + (size_t)(1 + 2 * q + half) * L.pitch * 4,
-                                            L.row_bytes, words.data() + half * n, (size_t)nx * 4,
-                                            (size_t)nx * 4, (size_t)ny, hipMemcpyHostToDevice, st));
-                HIPCHK(hipStreamSynchronize(st));  // words is reused
+                                            L.row_bytes, band + (size_t)half * n * 4, (size_t)nx * 4,
+                                            (size_t)nx * 4, (size_t)ny, hipMemcpyDeviceToDevice, st));
             }
+            HIPCHK(hipStreamSynchronize(st));  // the band plane and words are reused
         }
+        HIPCHK(hipMemcpyAsync(band, stage.data(), n * 8, hipMemcpyHostToDevice, st));
         const double* d_phi0 = reinterpret_cast<const double*>(v.band);
         HIPCHK(launch_init_state(v, d_phi0, nullptr, nullptr, nullptr, st));
         HIPCHK(hipStreamSynchronize(st));

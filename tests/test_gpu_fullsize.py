@@ -215,3 +215,50 @@ def test_widest_lattice_against_oracle(storage, inplace, tiles, tol):
             err = np.abs(gw - ow).max() / scale
             say(f"  window at x = {x0}: {fname} err {err:.2e}")
             assert err <= tol, (x0, fname, err)
+
+
+def test_tallest_lattice_in_place_where_two_buffers_do_not_fit():
+    """3 x 2^24 (the most rows the library accepts), FP64: the two-buffer layout
+    needs more than the device holds; the in-place update fits and matches the
+    oracle on windows at the bottom (across the periodic seam in y), the middle
+    and the top."""
+    import torch
+    nx, ny = 3, 1 << 24
+    p = wl.params(nx, ny, 1.2, 0.8, "mrt")
+    need_ab = lbm.lb_workspace_bytes(lbm.make_params(p, "f64"))
+    need_ip = lbm.lb_workspace_bytes(lbm.make_params(p, "f64", inplace=1))
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    say(f"case tallest lattice {nx}x{ny}: two buffers {need_ab / 2**30:.0f} GiB, in place "
+        f"{need_ip / 2**30:.0f} GiB, device {total / 2**30:.0f} GiB ({free / 2**30:.0f} free)")
+    assert need_ab > total
+    if need_ip > free:
+        pytest.skip("not enough free device memory for the in-place layout")
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    phi0 = np.tanh(1.5 * (np.sin(2 * np.pi * y / 40 + 0.9 * x) + 0.3 * np.sin(2 * np.pi * y / 13)))
+    inp = {"solid": np.zeros((ny, nx), dtype=np.uint8), "dphi": None, "phi0": phi0,
+           "rho0": 1.0 + 0.01 * np.sin(2 * np.pi * y / 29) + 0 * x,
+           "ux0": 0.01 * np.cos(2 * np.pi * y / 31) + 0 * x, "uy0": np.zeros((ny, nx))}
+    say("  inputs ready")
+    lat = lbm.lb_init(lbm.make_params(p, "f64", inplace=1), inp["solid"], inp["phi0"],
+                      rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+    say("  initialised")
+    lbm.lb_set_tuning(lat, 64, 32)
+    lbm.lb_step(lat, K)
+    fields = lbm.lb_read_fields(lat)
+    lat.close()
+    torch.cuda.empty_cache()
+    say("  GPU run done")
+    for y0 in (ny - W // 2, ny // 2, ny - W):
+        ys = np.arange(y0, y0 + W) % ny
+        sub = {k: (None if v is None else v[ys, :].copy()) for k, v in inp.items()}
+        orc = make_oracle(dict(p, ny=W), sub)
+        orc.step(K)
+        for fname, g, o in zip(("phi", "rho", "ux", "uy"), fields, orc.fields()):
+            gw = g[ys[MARGIN:W - MARGIN], :]
+            ow = o[MARGIN:W - MARGIN, :]
+            scale = max(np.abs(ow).max(), 1e-300) if fname in ("phi", "rho") else 1.0
+            err = np.abs(gw - ow).max() / scale
+            say(f"  window at y = {y0}: {fname} err {err:.2e}")
+            assert err <= 1e-12, (y0, fname, err)
