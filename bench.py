@@ -13,9 +13,11 @@ and contact angle within 0.5 degrees after 10^4 steps).
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 
 Prints one JSON line. `roofline` reports the dominant kernel (the sweep):
-algorithmic bytes (36 populations read and written per lattice update) over the
-average launch duration measured with HIP events on the stream the kernels run
-on. `traffic` is the HBM rate from the committed rocprofv3 counter summary
+algorithmic bytes (36 populations read and written per lattice update: 288 B in
+FP64, 144 B in FP32, 74 B in the 16-bit formats) over the average launch
+duration measured with HIP events on the stream the kernels run on;
+`frac_stored` repeats it with the bytes the stored layout moves (88 B in the
+16-bit formats, whose f_0, f_1, f_3 are 32-bit). `traffic` is the HBM rate from the committed rocprofv3 counter summary
 (profiles/sweep_traffic_4096x2048.json: FETCH_SIZE + WRITE_SIZE per launch,
 calibrated on a copy of known size) over the same launch duration, reported
 only while the kernel sources hash as they did when the counters were taken.
@@ -36,9 +38,16 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + HBM GB/s at stated angle/\u03c6 error: FP32/BF16 & batched vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096x2048.json")
 PEAK_HBM_GBS = 8000.0
-# "ip": the same format updated in place in one buffer (same algorithmic bytes).
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88, "f64c": 208, "f32c": 104,
+# Algorithmic bytes per lattice update: 18 populations read once and written
+# once, at the element size of the format (16-bit formats: 74 B, i.e. 72 B for
+# 36 two-byte populations plus 2 B for g_0, which is kept in 32 bits; the
+# compressed-g formats: f and the four-value g-state). "ip": the same format
+# updated in place in one buffer (same algorithmic bytes).
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 74, "bf16s": 74, "f64c": 208, "f32c": 104,
                 "f64ip": 288, "f32ip": 144}
+# Bytes the stored layout moves per lattice update (the 16-bit formats keep
+# f_0, f_1, f_3 and g_0 in 32 bits: 44 B per node per buffer).
+STORED_BYTES_PER_LU = dict(BYTES_PER_LU, f16s=88, bf16s=88)
 ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32", "f64c": "f64", "f32c": "f32",
          "f64ip": "f64", "f32ip": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
@@ -137,6 +146,11 @@ def main():
     fluid = int((inp["solid"] == 0).sum())
     storages = [s for s in args.storages.split(",") if s]
     results = {}
+    # Every lattice is created (host staging, S_0) before any is timed, so the
+    # timed legs run back to back: an idle GPU drops its shader clock, and a
+    # 20-step window after host-side set-up would time the clock ramp (up to 12%
+    # on the formats that are limited by instruction issue), not the sweep.
+    lats = {}
     for st in storages:
         lat = make_lattice(lbm, p, inp, st)
         if args.autotune:
@@ -146,20 +160,28 @@ def main():
                         else DEFAULT_TILES[st])
             lbm.lb_set_tuning(lat, bx, rows)
             tune = (bx, rows)
+        lats[st] = (lat, tune)
+    torch.cuda.synchronize()
+    for st in storages:
+        lat, tune = lats[st]
         ms, wall_ms = time_steps(torch, lbm, lat, args.steps, args.warmup)
         d = lbm.lb_diagnostics(lat, check=False)
         ms_step = ms / args.steps
         mlups = nodes / (ms_step * 1e-3) / 1e6
         gbs = BYTES_PER_LU[st] * nodes / (ms_step * 1e-3) / 1e9
+        gbs_stored = STORED_BYTES_PER_LU[st] * nodes / (ms_step * 1e-3) / 1e9
         results[st] = dict(ms_per_step=ms_step, mlups=mlups, gbs=gbs,
                            mlups_fluid=fluid / (ms_step * 1e-3) / 1e6,
-                           frac=gbs / PEAK_HBM_GBS, tiles=list(tune),
+                           frac=gbs / PEAK_HBM_GBS, gbs_stored=gbs_stored,
+                           frac_stored=gbs_stored / PEAK_HBM_GBS, tiles=list(tune),
                            wall_ms_per_step=wall_ms / args.steps,
                            finite=bool(d["rc"] == 0))
         log(f"{st}: {ms_step:.4f} ms/step  {mlups:.0f} MLUPS  {gbs:.0f} GB/s "
             f"({100 * gbs / PEAK_HBM_GBS:.1f}% of 8 TB/s)  tiles {tune}")
-        lat.close()
-        torch.cuda.empty_cache()
+    for st in storages:
+        lats[st][0].close()
+    lats.clear()
+    torch.cuda.empty_cache()
 
     # Accuracy of each reduced-precision format against FP64 after validate_steps.
     accuracy = {}
@@ -249,14 +271,21 @@ def main():
                    "speedup_vs_f64": round(r["mlups"] / results["f64"]["mlups"], 3)
                    if "f64" in results else None},
         "roofline": {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": traffic_gbs(head),
+                     "unit": "GB/s", "frac": round(r["frac"], 4),
+                     "bytes_per_lu": BYTES_PER_LU[head],
+                     "achieved_stored": round(r["gbs_stored"], 1),
+                     "frac_stored": round(r["frac_stored"], 4),
+                     "stored_bytes_per_lu": STORED_BYTES_PER_LU[head],
+                     "traffic": traffic_gbs(head),
                      "traffic_ratio": (round(traffic[head]["ratio"], 4)
                                        if traffic and head in traffic else None),
                      "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1)},
         "variants": {s: {"mlups": round(v["mlups"], 1), "mlups_fluid": round(v["mlups_fluid"], 1),
                          "ms_per_step": round(v["ms_per_step"], 5),
                          "gbs": round(v["gbs"], 1), "frac": round(v["frac"], 4),
-                         "bytes_per_lu": BYTES_PER_LU[s], "tiles": v["tiles"],
+                         "bytes_per_lu": BYTES_PER_LU[s],
+                         "frac_stored": round(v["frac_stored"], 4),
+                         "stored_bytes_per_lu": STORED_BYTES_PER_LU[s], "tiles": v["tiles"],
                          "traffic_gbs": traffic_gbs(s),
                          **({k: (float(f"{x:.4g}") if isinstance(x, float) else x)
                              for k, x in accuracy.get(s, {}).items()})}

@@ -187,7 +187,11 @@ int lb_init_ext(const lb_params* p, const uint8_t* solid, const double* wall_dph
                 const double* phi0, const double* rho0, const double* ux0, const double* uy0,
                 void* stream, void* device_buffer, size_t buffer_bytes, lb_handle** out);
 
-/* Enqueue nsteps >= 0 timesteps on the handle's stream; does not block. */
+/* Enqueue nsteps >= 0 timesteps on the handle's stream; does not block. The
+ * steps are replayed from HIP graphs that the first call captures (on an
+ * internal stream; windows of 1, 2, 4, ..., 32 steps for either parity, with
+ * and without the periodic check at their first step), so every later call,
+ * of any length, replays graphs only. */
 int lb_step(lb_handle* h, int64_t nsteps);
 
 /* Synchronise and copy the moments of S_n (Eq. (moments)) to host arrays of
@@ -227,7 +231,9 @@ int lb_fill_length(lb_handle* h, int32_t x_lo, int32_t x_hi, double width, doubl
 int lb_set_wall_dphi(lb_handle* h, const double* wall_dphi);
 
 /* Write / read a checkpoint: parameters, step count, mask, wall field and the
- * device state, bit for bit. lb_load needs a handle of identical parameters. */
+ * device state, bit for bit. lb_load needs a handle of identical parameters;
+ * it clears the handle's record of an earlier non-finite periodic check, so a
+ * handle that blew up can resume from a good checkpoint. */
 int lb_save(lb_handle* h, const char* path);
 int lb_load(lb_handle* h, const char* path);
 
@@ -252,10 +258,13 @@ const char* lb_last_error(void);
  * B = -A > 0. */
 int lb_dphi_for_angle(double theta_deg, double kappa, double A, double B, double* dphi);
 
-/* HBM ceiling of the device: time `repeats` streaming copies of `bytes`
- * (>= 1 MiB) between two scratch buffers it allocates and frees, and return
- * the read + write rate in GB/s. A reference for the sweep's achieved
- * bandwidth, not part of the method. */
+/* Streaming-copy rate of the device: time `repeats` copies of `bytes`
+ * (>= 1 MiB) between two scratch buffers it allocates and frees, with three
+ * copy kernels (one 16-byte element per thread and iteration; four in flight
+ * with nontemporal stores; four with nontemporal loads and stores) at 2, 4, 8
+ * and 16 workgroups of 256 threads per CU, and return the best read + write
+ * rate in GB/s. A reference for the sweep's achieved bandwidth, not part of the
+ * method. */
 int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs);
 
 /*

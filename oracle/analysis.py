@@ -156,3 +156,89 @@ def flat_profile(phi_init, A, B, kappa, iters=60):
         if np.max(np.abs(step)) < 1e-15:
             break
     return phi, mu0
+
+
+# ---------------------------------------------------------------- flat walls
+
+def _walled_newton(phi, A, B, kappa, d_lo, d_hi, total, iters=80):
+    """Newton solve of A phi + B phi^3 - kappa L phi = mu0 on the fluid rows
+    1..n of a channel whose solid rows 0 and n+1 carry the ghost values of the
+    wall condition (Sec. II, d_perp phi = xi / kappa, the gradient taken across
+    the mid-link wall plane): phi_0 = phi_1 - d_lo, phi_{n+1} = phi_n - d_hi.
+    L phi_j = phi_{j+1} + phi_{j-1} - 2 phi_j is Eq. (best) on a field constant
+    along the wall. With `total` given, sum(phi) is fixed and mu0 is an unknown;
+    otherwise mu0 = 0 and the far end (d_hi = None) is held at its bulk value."""
+    phi = np.array(phi, dtype=float)
+    n = phi.size
+    fixed_far = d_hi is None
+    far = phi[-1]
+    mu0 = 0.0
+    m = n + (1 if total is not None else 0)
+    for _ in range(iters):
+        lo = phi[0] - d_lo
+        hi = far if fixed_far else phi[-1] - d_hi
+        ext = np.concatenate([[lo], phi, [hi]])
+        lap = ext[2:] + ext[:-2] - 2.0 * phi
+        res = A * phi + B * phi ** 3 - kappa * lap - mu0
+        J = np.zeros((m, m))
+        idx = np.arange(n)
+        J[idx, idx] = A + 3.0 * B * phi ** 2 + 2.0 * kappa
+        J[idx[:-1], idx[:-1] + 1] -= kappa
+        J[idx[1:], idx[1:] - 1] -= kappa
+        J[0, 0] -= kappa                 # the ghost phi_0 follows phi_1
+        if not fixed_far:
+            J[n - 1, n - 1] -= kappa     # the ghost phi_{n+1} follows phi_n
+        if total is not None:
+            J[idx, n] = -1.0
+            J[n, :n] = 1.0
+            res = np.concatenate([res, [phi.sum() - total]])
+        step = np.linalg.solve(J, -res)
+        phi += step[:n]
+        if total is not None:
+            mu0 += step[n]
+        if np.max(np.abs(step)) < 1e-15:
+            break
+    return phi, mu0
+
+
+def wall_film_profile(phi_init, A, B, kappa, d_lo, d_hi):
+    """The discrete equilibrium across a channel between two flat walls with
+    wall gradients d_lo (bottom) and d_hi (top), at the total phi of phi_init
+    (the fluid rows only). Returns (phi, mu0)."""
+    phi_init = np.asarray(phi_init, dtype=float)
+    return _walled_newton(phi_init, A, B, kappa, d_lo, d_hi, phi_init.sum())
+
+
+def wall_tension(dphi, bulk, A, B, kappa, n=80):
+    """Tension of a flat wall against the bulk phase phi = bulk (+1 or -1) in the
+    discrete free energy whose stationary points the lattice reaches: the sum
+    over fluid rows of psi(phi) - psi(bulk), the gradient energy kappa/2 (dphi)^2
+    of every link between fluid rows, and the surface term xi phi_1 of Sec. II,
+    xi = kappa d_perp phi, at the first fluid row. Its stationarity condition at
+    row 1 is the chemical potential with the ghost row phi_0 = phi_1 - d_perp phi."""
+    phi, _ = _walled_newton(np.full(n, float(bulk)), A, B, kappa, dphi, None, None)
+    psi = lambda p: 0.5 * A * p ** 2 + 0.25 * B * p ** 4
+    ext = np.concatenate([phi, [float(bulk)]])
+    return ((psi(phi) - psi(float(bulk))).sum() + 0.5 * kappa * (np.diff(ext) ** 2).sum()
+            + kappa * dphi * phi[0])
+
+
+def discrete_interface_tension(A, B, kappa, n=400):
+    """Tension of a flat interface in the same discrete free energy (bulk
+    energy per node plus kappa/2 (dphi)^2 per link), from the Newton profile."""
+    a = -A
+    x = np.arange(float(n))
+    w = math.sqrt(2.0 * kappa / a)
+    prof, _ = flat_profile(np.tanh((n / 4 - np.abs(x - (n - 1) / 2)) / w), A, B, kappa)
+    psi = lambda p: 0.5 * A * p ** 2 + 0.25 * B * p ** 4 - (0.5 * A + 0.25 * B)
+    return 0.5 * (psi(prof).sum() + 0.5 * kappa * ((np.roll(prof, -1) - prof) ** 2).sum())
+
+
+def discrete_young_angle(dphi, A, B, kappa):
+    """Young's law, Eq. (Young), with the wall and interface tensions of the
+    discrete free energy: the equilibrium angle (degrees, through phi > 0) that
+    the lattice's wetting condition implies for a drop large against W."""
+    g_as = wall_tension(dphi, 1.0, A, B, kappa)
+    g_bs = wall_tension(dphi, -1.0, A, B, kappa)
+    c = (g_bs - g_as) / discrete_interface_tension(A, B, kappa)
+    return math.degrees(math.acos(max(-1.0, min(1.0, c))))

@@ -51,7 +51,8 @@ struct Range {
 
 constexpr int kEX[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
 constexpr int kEY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
-constexpr int kGraphSteps = 32;  // timesteps per captured graph (even: parity returns)
+constexpr int kGraphSteps = 32;  // longest window of timesteps in one captured graph
+constexpr int kGraphLens = 6;    // windows of 1, 2, 4, ..., 32 steps
 constexpr int kBatchTuneSteps = 4;  // timed steps per candidate when lb_batch_init tunes
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -139,8 +140,9 @@ struct Group {
     View* d_views = nullptr;
     int n_tiles = 0;
     char* batch_alloc = nullptr;
-    // cached graphs keyed by whether the graph carries the periodic check
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // Captured graphs, one per (window length 2^l, parity of its first step,
+    // whether its first step carries the periodic check): index (l*2 + parity)*2 + check.
+    hipGraphExec_t graph[kGraphLens * 4] = {};
     bool batched = false;
     bool any_walls = false;  // a batch member uses lattice-node bounce-back
 };
@@ -482,57 +484,71 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
                            g.d_flag, st);
 }
 
+// Capture `len` timesteps starting at `parity`, the first with the periodic
+// check when `check`, into one executable graph.
+int capture_graph(Group& g, int len, int parity, bool check, hipGraphExec_t* out) {
+    Range r("lb graph capture");
+    if (!g.capture_stream)
+        HIPCHK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
+    hipError_t ce = hipSuccess;
+    for (int s = 0; s < len && ce == hipSuccess; ++s)
+        ce = enqueue_one(g, check && s == 0, (parity + s) & 1, g.capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(g.capture_stream, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(LB_EHIP, std::string("graph capture failed: ") +
+                                 hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        *out = nullptr;
+        return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    // Move the graph's launch data to the device now, not at its first replay.
+    HIPCHK(hipGraphUpload(*out, g.stream));
+    return LB_OK;
+}
+
+// Every step runs from a captured graph. A call is cut into windows of 2^l
+// steps (at most kGraphSteps) whose only periodic check, if any, is at their
+// first step; each window replays the graph of its length, starting parity and
+// check. All graphs of a group are captured together the first time it steps
+// (and again after a change of tiles), so that a later call of any length and
+// phase replays graphs only.
 int group_step(Group& g, int64_t nsteps) {
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return LB_OK;
     const int de = g.m[0].p.diag_every;
-    auto is_diag = [&](int64_t s) { return de > 0 && s % de == 0; };
-    int64_t left = nsteps;
-    // A window of kGraphSteps steps replays a captured graph when it starts at
-    // parity 0 and its checks fall where the graph has them: graph 1 checks at
-    // every window step s with s % de == 0 (only s = 0 when de >= kGraphSteps),
-    // graph 0 never. Other steps are launched one by one.
-    auto window_key = [&]() -> int {
-        if (left < kGraphSteps || g.parity != 0) return -1;
-        if (de == 0) return 0;
-        if (g.step % de == 0 && (kGraphSteps % de == 0 || de >= kGraphSteps)) return 1;
-        if (de >= kGraphSteps && g.step - g.step % de + de >= g.step + kGraphSteps) return 0;
-        return -1;
-    };
-    while (left > 0) {
-        const int key = window_key();
-        if (key >= 0) {
-            if (!g.graph[key]) {
-                Range r("lb graph capture");
-                if (!g.capture_stream)
-                    HIPCHK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
-                HIPCHK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
-                hipError_t ce = hipSuccess;
-                for (int s = 0; s < kGraphSteps && ce == hipSuccess; ++s)
-                    ce = enqueue_one(g, key == 1 && s % de == 0, s & 1, g.capture_stream);
-                hipGraph_t graph = nullptr;
-                hipError_t ee = hipStreamEndCapture(g.capture_stream, &graph);
-                if (ce != hipSuccess || ee != hipSuccess) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return fail(LB_EHIP, std::string("graph capture failed: ") +
-                                             hipGetErrorString(ce != hipSuccess ? ce : ee));
+    if (!g.graph[0]) {
+        for (int l = 0; l < kGraphLens; ++l)
+            for (int par = 0; par < 2; ++par)
+                for (int chk = 0; chk < (de > 0 ? 2 : 1); ++chk) {
+                    int rc = capture_graph(g, 1 << l, par, chk != 0,
+                                           &g.graph[(l * 2 + par) * 2 + chk]);
+                    if (rc) {
+                        destroy_graphs(g);
+                        return rc;
+                    }
                 }
-                hipError_t ie = hipGraphInstantiate(&g.graph[key], graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (ie != hipSuccess)
-                    return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-            }
-            {
-                Range r("lb graph replay");
-                HIPCHK(hipGraphLaunch(g.graph[key], g.stream));
-            }
-            g.step += kGraphSteps;
-            left -= kGraphSteps;
-            continue;
+    }
+    int64_t left = nsteps;
+    while (left > 0) {
+        int64_t lim = std::min<int64_t>(left, kGraphSteps);
+        if (de > 0) lim = std::min<int64_t>(lim, de - g.step % de);
+        int l = 0;
+        while ((int64_t)2 << l <= lim) ++l;
+        const bool chk = de > 0 && g.step % de == 0;
+        {
+            Range r("lb graph replay");
+            HIPCHK(hipGraphLaunch(g.graph[(l * 2 + g.parity) * 2 + (chk ? 1 : 0)], g.stream));
         }
-        HIPCHK(enqueue_one(g, is_diag(g.step), g.parity, g.stream));
-        g.parity ^= 1;
-        g.step += 1;
-        left -= 1;
+        const int len = 1 << l;
+        g.parity = (g.parity + len) & 1;
+        g.step += len;
+        left -= len;
     }
     return LB_OK;
 }
@@ -810,7 +826,11 @@ int set_tuning(Group& g, int bx, int rows) {
 std::mutex g_tune_mu;
 // Keyed by the current device's architecture name as well as the problem, so
 // one process driving devices of different kinds tunes each.
-std::map<std::tuple<std::string, int, int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
+// The kernel variant is part of the problem: tau_phi = 1 selects its own sweep
+// instance, lattice-node bounce-back adds the wall launch and the tau table
+// changes the per-node arithmetic.
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int, int, int>;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
 int autotune(Group& g, int steps, lb_tuning* chosen) {
     Range range("lb autotune");
@@ -821,9 +841,14 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     int max_ny = 0, total = 0;
     for (auto& mb : g.m) { max_ny = std::max(max_ny, mb.p.ny); total += mb.p.nx * mb.p.ny; }
-    const auto key = std::make_tuple(std::string(prop.gcnArchName), g.m[0].p.nx, max_ny,
-                                     g.m[0].p.storage, g.m[0].p.collision, g.m[0].p.inplace,
-                                     g.batched ? total : -1);
+    int any_bounce = 0, any_lut = 0;
+    for (auto& mb : g.m) {
+        any_bounce |= mb.p.bounce == LB_LATTICE_NODE;
+        any_lut |= mb.p.tau_lut > 1;
+    }
+    const TuneKey key(std::string(prop.gcnArchName), g.m[0].p.nx, max_ny, g.m[0].p.storage,
+                      g.m[0].p.collision, g.m[0].p.inplace, g.batched ? total : -1,
+                      g.m[0].p.tau_phi == 1.0, any_bounce, any_lut);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -1074,6 +1099,9 @@ int lb_load(lb_handle* h, const char* path) {
         return fail(LB_EINVAL, "checkpoint parameters or mask differ from the handle");
     HIPCHK(hipStreamSynchronize(g.stream));
     HIPCHK(hipMemcpy(mb.view.buf[0], buf.data(), buf.size(), hipMemcpyHostToDevice));
+    // The loaded state replaces whatever the periodic check saw before: clear
+    // the sticky non-finite flag (and its scratch neighbour).
+    HIPCHK(launch_fill(mb.base + mb.L.off_flag, 0, 8, g.stream));
     g.parity = hd.parity;
     g.step = hd.step;
     return upload_dphi(mb, dphi.data(), g.stream);
@@ -1139,23 +1167,32 @@ int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs)
             rc = fail(LB_EHIP, "device query failed");
             break;
         }
-        const int blocks = cus * 16;
-        if (launch_fill(a, 1, bytes, st) != hipSuccess ||
-            launch_stream_copy(a, b, bytes, blocks, st) != hipSuccess ||
-            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-            hipEventRecord(e0, st) != hipSuccess) {
+        if (launch_fill(a, 1, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
             rc = fail(LB_EHIP, "probe launch failed");
             break;
         }
-        for (int r = 0; r < repeats && rc == LB_OK; ++r)
-            if (launch_stream_copy(a, b, bytes, blocks, st) != hipSuccess)
+        // Three copy kernels at four grid sizes (workgroups per CU); the best rate.
+        double best = 0.0;
+        for (int cfg = 0; cfg < 12 && rc == LB_OK; ++cfg) {
+            const int variant = cfg / 4, blocks = cus * (2 << (cfg % 4));
+            if (launch_stream_copy(a, b, bytes, blocks, variant, st) != hipSuccess ||
+                hipEventRecord(e0, st) != hipSuccess) {
                 rc = fail(LB_EHIP, "probe launch failed");
-        float ms = 0;
-        if (rc == LB_OK && (hipEventRecord(e1, st) != hipSuccess ||
-                            hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = fail(LB_EHIP, "probe timing failed");
-        if (rc == LB_OK) *gbs = 2.0 * (double)bytes * repeats / (ms * 1e-3) / 1e9;
+                break;
+            }
+            for (int r = 0; r < repeats && rc == LB_OK; ++r)
+                if (launch_stream_copy(a, b, bytes, blocks, variant, st) != hipSuccess)
+                    rc = fail(LB_EHIP, "probe launch failed");
+            float ms = 0;
+            if (rc == LB_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(LB_EHIP, "probe timing failed");
+            if (rc != LB_OK) break;
+            best = std::max(best, 2.0 * (double)bytes * repeats / (ms * 1e-3) / 1e9);
+        }
+        if (rc == LB_OK) *gbs = best;
     } while (0);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

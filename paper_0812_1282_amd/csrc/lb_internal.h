@@ -134,7 +134,7 @@ hipError_t launch_read_plane(const View& v, int parity, int plane, double* out,
 hipError_t launch_crossings(const View& v, int parity, void* points, int64_t capacity,
                             unsigned long long* counter, hipStream_t stream);
 hipError_t launch_fill(void* dst, uint8_t value, size_t bytes, hipStream_t stream);
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks, int variant,
                               hipStream_t stream);
 
 struct Crossing {

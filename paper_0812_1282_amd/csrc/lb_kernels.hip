@@ -1954,20 +1954,37 @@ __global__ __launch_bounds__(256) void crossings_kernel(View v, int parity,
     }
 }
 
-// Streaming copy used to measure the HBM read+write ceiling of the device.
+// Streaming copies used as a reference for the device's HBM read + write rate.
+// Variant 0: one 16-byte element per thread and iteration, plain loads and
+// stores; 1: four elements in flight per thread, plain loads, nontemporal
+// stores (as the sweep stores); 2: four elements, nontemporal loads and stores.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int V>
 __global__ __launch_bounds__(256) void stream_copy_kernel(const f32x4* __restrict__ src,
                                                           f32x4* __restrict__ dst, size_t n) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (V > 0) {
+        for (; i + 3 * stride < n; i += 4 * stride) {
+            f32x4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                v[u] = V == 2 ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+        }
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks, int variant,
                               hipStream_t stream) {
-    hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, stream,
-                       reinterpret_cast<const f32x4*>(src), reinterpret_cast<f32x4*>(dst),
-                       bytes / sizeof(f32x4));
+    const f32x4* a = reinterpret_cast<const f32x4*>(src);
+    f32x4* b = reinterpret_cast<f32x4*>(dst);
+    const size_t n = bytes / sizeof(f32x4);
+    if (variant == 0) hipLaunchKernelGGL(stream_copy_kernel<0>, dim3(blocks), dim3(256), 0, stream, a, b, n);
+    else if (variant == 1) hipLaunchKernelGGL(stream_copy_kernel<1>, dim3(blocks), dim3(256), 0, stream, a, b, n);
+    else hipLaunchKernelGGL(stream_copy_kernel<2>, dim3(blocks), dim3(256), 0, stream, a, b, n);
     return hipGetLastError();
 }
 
