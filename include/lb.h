@@ -207,6 +207,18 @@ int lb_read_populations(lb_handle* h, double* f, double* g);
  * is not finite. */
 int lb_diagnostics(lb_handle* h, lb_diag* d);
 
+/* lb_diagnostics without allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same reduction kernels and the same result bit for bit; the
+ * per-block partial sums, the finished record and a flag word live in a fixed
+ * device array of the library (2 MiB + 320 bytes, 2^15 records of 256 nodes;
+ * each GPU the library runs on holds its own copy until the process ends)
+ * instead of the lattice's memory. Lattices of at most 2^23 nodes (LB_EINVAL
+ * beyond). The array keeps the last call's contents and is shared by every
+ * call on that GPU: calls that overlap on one GPU (several threads or streams)
+ * race. Synchronises the handle's stream. */
+int lb_diagnostics_noalloc(lb_handle* h, lb_diag* d);
+
 /*
  * Contact angle (Sec. IV): every axis link between two fluid nodes whose phi
  * values have opposite signs gives the phi = 0 crossing by linear

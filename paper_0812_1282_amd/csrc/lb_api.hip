@@ -111,6 +111,39 @@ Layout make_layout(int nx, int ny, int storage, bool inplace) {
 
 }  // namespace lbm
 
+// Scratch of lb_diagnostics_noalloc: the per-block partial records of the
+// moments reduction, the finished record and a flag word, in a file-scope device
+// array instead of the lattice's arena, so that the call allocates nothing.
+// Every GPU the library runs on holds its own copy until the process ends.
+constexpr size_t kScratchRecords = (size_t)1 << 15;  // one per 256 nodes: up to 2^23 nodes
+constexpr size_t kScratchBytes = (kScratchRecords + 1) * kPartials * 8 + 256;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device. In host code the
+// array's name is only a stand-in for the symbol, not a device address: it is
+// resolved once per device with hipGetSymbolAddress, with that device current,
+// and only the resolved pointer is handed to kernels.
+int scratch_address(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EHIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LB_EHIP, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+}  // namespace
+
 struct Member {
     lb_params p;
     Layout L;
@@ -576,15 +609,15 @@ int read_fields(Group& g, int k, double* phi, double* rho, double* ux, double* u
     Member& mb = g.m[k];
     const int64_t n = (int64_t)mb.p.nx * mb.p.ny;
     const auto sc = scratch_of(g, mb);
-    double* scratch = reinterpret_cast<double*>(sc.first);
+    double* stage = reinterpret_cast<double*>(sc.first);
     const int64_t chunk = std::min<int64_t>(n, (int64_t)(sc.second / 32));
     double* outs[4] = {phi, rho, ux, uy};
     for (int64_t first = 0; first < n; first += chunk) {
         const int64_t cnt = std::min(chunk, n - first);
-        HIPCHK(launch_moments(mb.view, g.parity, first, cnt, scratch, nullptr, 0, 0, 0, g.stream));
+        HIPCHK(launch_moments(mb.view, g.parity, first, cnt, stage, nullptr, 0, 0, 0, g.stream));
         for (int q = 0; q < 4; ++q)
             if (outs[q])
-                HIPCHK(hipMemcpyAsync(outs[q] + first, scratch + q * cnt, cnt * 8,
+                HIPCHK(hipMemcpyAsync(outs[q] + first, stage + q * cnt, cnt * 8,
                                       hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
     }
@@ -594,12 +627,12 @@ int read_fields(Group& g, int k, double* phi, double* rho, double* ux, double* u
 int read_populations(Group& g, int k, double* f, double* gg) {
     Member& mb = g.m[k];
     const size_t n = (size_t)mb.p.nx * mb.p.ny;
-    double* scratch = reinterpret_cast<double*>(scratch_of(g, mb).first);
+    double* stage = reinterpret_cast<double*>(scratch_of(g, mb).first);
     for (int pl = 0; pl < 18; ++pl) {
         double* out = pl < 9 ? f : gg;
         if (!out) continue;
-        HIPCHK(launch_read_plane(mb.view, g.parity, pl, scratch, g.stream));
-        HIPCHK(hipMemcpyAsync(out + (size_t)(pl % 9) * n, scratch, n * 8, hipMemcpyDeviceToHost,
+        HIPCHK(launch_read_plane(mb.view, g.parity, pl, stage, g.stream));
+        HIPCHK(hipMemcpyAsync(out + (size_t)(pl % 9) * n, stage, n * 8, hipMemcpyDeviceToHost,
                               g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
     }
@@ -1013,6 +1046,42 @@ int lb_diagnostics(lb_handle* h, lb_diag* d) {
     if (!is_finite(s[0]) || !is_finite(s[1]) || !is_finite(s[2]) || !(s[3] == s[3]))
         return fail(LB_ENUMERIC, "non-finite conservation sums");
     return check_flag(h->g);
+}
+
+int lb_diagnostics_noalloc(lb_handle* h, lb_diag* d) {
+    if (!h || !d) return fail(LB_EINVAL, "NULL argument");
+    Group& g = h->g;
+    Member& mb = g.m[0];
+    const int64_t n = (int64_t)mb.p.nx * mb.p.ny;
+    const int64_t nrec = (n + 255) / 256;
+    if (nrec > (int64_t)kScratchRecords)
+        return fail(LB_EINVAL, "lb_diagnostics_noalloc takes lattices of at most 2^23 nodes "
+                               "(its scratch holds 2^15 partial records of 256 nodes)");
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    double* partials = reinterpret_cast<double*>(base);
+    double* rec_dev = partials + kScratchRecords * kPartials;
+    int32_t* flag = reinterpret_cast<int32_t*>(rec_dev + kPartials);
+    // The array keeps the last call's contents: the flag word must start at
+    // zero (a fill kernel, so the call can also sit inside a captured graph);
+    // the partial records and the finished record are written in full below.
+    HIPCHK(launch_fill(flag, 0, 4, g.stream));
+    HIPCHK(launch_moments(mb.view, g.parity, 0, n, nullptr, partials, (int)kScratchRecords, 0, 0,
+                          g.stream));
+    HIPCHK(launch_finalize(nullptr, nullptr, 1, (int)nrec, partials, rec_dev, flag, g.stream));
+    double rec[kPartials];
+    HIPCHK(hipMemcpyAsync(rec, rec_dev, sizeof(rec), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    d->sum_rho = rec[0];
+    d->sum_phi = rec[1];
+    d->kinetic = rec[2];
+    d->max_u = rec[3];
+    d->n_fluid = (int64_t)std::llround(rec[4]);
+    d->step = g.step;
+    if (!is_finite(rec[0]) || !is_finite(rec[1]) || !is_finite(rec[2]) || !(rec[3] == rec[3]))
+        return fail(LB_ENUMERIC, "non-finite conservation sums");
+    return check_flag(g);
 }
 
 int lb_contact_angle(lb_handle* h, double x_lo, double x_hi, double y_lo, double y_hi,

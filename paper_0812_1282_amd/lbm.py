@@ -29,7 +29,7 @@ EXPORTS = [
     "lb_get_tuning", "lb_autotune", "lb_get_step", "lb_free", "lb_last_error",
     "lb_dphi_for_angle", "lb_batch_init", "lb_batch_step", "lb_batch_read_fields",
     "lb_batch_read_populations", "lb_batch_contact_angle", "lb_batch_get_tuning",
-    "lb_batch_free", "lb_bandwidth_probe", "lb_batch_autotune",
+    "lb_batch_free", "lb_bandwidth_probe", "lb_batch_autotune", "lb_diagnostics_noalloc",
 ]
 
 
@@ -95,6 +95,7 @@ def load_library(path=LIB_PATH):
         "lb_read_fields": [_VP, _D, _D, _D, _D],
         "lb_read_populations": [_VP, _D, _D],
         "lb_diagnostics": [_VP, ctypes.POINTER(lb_diag)],
+        "lb_diagnostics_noalloc": [_VP, ctypes.POINTER(lb_diag)],
         "lb_contact_angle": [_VP, dbl, dbl, dbl, dbl, dbl, i32, _D, _D, _D, _D,
                              ctypes.POINTER(i64)],
         "lb_fill_length": [_VP, i32, i32, dbl, _D],
@@ -249,6 +250,17 @@ def lb_read_populations(lat):
 def lb_diagnostics(lat, check=True):
     d = lb_diag()
     rc = load_library().lb_diagnostics(lat._h, ctypes.byref(d))
+    if check:
+        _check(rc)
+    return {"sum_rho": d.sum_rho, "sum_phi": d.sum_phi, "kinetic": d.kinetic, "max_u": d.max_u,
+            "n_fluid": d.n_fluid, "step": d.step, "rc": rc}
+
+
+def lb_diagnostics_noalloc(lat, check=True):
+    """lb_diagnostics with its partial sums in the library's fixed device array
+    (allocates nothing; lattices up to 2^23 nodes)."""
+    d = lb_diag()
+    rc = load_library().lb_diagnostics_noalloc(lat._h, ctypes.byref(d))
     if check:
         _check(rc)
     return {"sum_rho": d.sum_rho, "sum_phi": d.sum_phi, "kinetic": d.kinetic, "max_u": d.max_u,
