@@ -184,17 +184,44 @@ def test_neutral_wall_unequal_viscosity_bgk_vs_mrt():
     assert res["bgk"] - res["mrt"] > 3.0
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_equilibrium_angle_equal_viscosity(theta):
-    """Fig. 2(a): with tau_alpha = tau_beta = 1 the measured angle follows Eq. (theory).
-    100 x 50 drop of radius 25 (the small workload), 5000 steps."""
-    p, inp = wl.c1_drop(seed=1, dphi_wall=an.theory_dphi(theta, KAPPA, A_L))
+def _converged_angle(theta, gamma, chunk=5000, n_chunks=6):
+    """A drop (R = 18 on a 128 x 48 channel, BGK, tau = 1, the wall gradient of
+    Eq. (theory) for theta) stepped until its measured angle settles; returns the
+    angles after each chunk of steps."""
+    p = wl.params(128, 48, 1.0, 1.0, "bgk", Gamma=gamma)
+    inp = wl.drop_on_wall(p, 18.0, 64.0, 0.0, 1, an.theory_dphi(theta, KAPPA, A_L))
     o = make_oracle(p, inp)
-    o.step(5000)
-    phi = o.fields()[0]
-    th = an.contact_angle(phi, inp["solid"], 0.5, 1, 0, 100, 3.5, 47)["theta"]
-    assert abs(th - theta) < 3.0
+    out = []
+    for _ in range(n_chunks):
+        o.step(chunk)
+        phi = o.fields()[0]
+        out.append(an.contact_angle(phi, inp["solid"], 0.5, 1, 0, 128, 3.5, 43.5)["theta"])
+    return out
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_converged_equilibrium_angle_follows_theory(theta):
+    """Fig. 2(a), Eq. (theory), tau_alpha = tau_beta = 1: a drop on a wetting wall
+    run to a steady angle (under 0.1 degree of change over the last 10^4 steps)
+    sits within 3 degrees of Eq. (theory) and on its side of 90 degrees.
+
+    The mobility is M = 1 (Gamma = 2). The steady angle is not a free-energy
+    minimum alone: mid-link bounce-back leaves y momentum at the wall nodes in
+    the interface (also at tau = 1), and the flow it drives at the contact line
+    moves phi against its diffusion, so the angle settles closer to the static
+    one the larger the mobility (at 60 degrees on this lattice: 53.8 degrees for
+    Gamma = 0.1, 56.3 for 0.5, 57.6 for 2; the static discrete value is 59.3,
+    test_discrete_young_angle_follows_theory). At 60 degrees the run at Gamma =
+    0.1 is repeated to hold that dependence."""
+    th = _converged_angle(theta, 2.0)
+    assert abs(th[-1] - th[-3]) < 0.1
+    assert abs(th[-1] - theta) < 3.0
+    assert (th[-1] - 90.0) * (theta - 90.0) >= 0.0 or abs(th[-1] - 90.0) < 1.0
+    if theta == 60.0:
+        lo = _converged_angle(theta, 0.1)
+        assert abs(lo[-1] - lo[-3]) < 0.1
+        assert th[-1] - lo[-1] > 2.5
 
 
 @pytest.mark.slow
