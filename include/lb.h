@@ -304,6 +304,29 @@ int lb_batch_contact_angle(lb_batch* b, int32_t member, double x_lo, double x_hi
                            double y_lo, double y_hi, double y_wall, int32_t wall_dir,
                            double* theta_deg);
 int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen);
+
+/* Schedule of a batch's timesteps. LB_SCHEDULE_STEPWISE: one launch per step over
+ * every member's tiles (the tile table above). LB_SCHEDULE_PERSISTENT: a window
+ * of steps (up to 32, the graph windows of lb_step) is one launch of as many
+ * workgroups as fit on the device, which take (step, tile) items in order from
+ * a counter and sweep a tile as soon as the tiles around it (within one tile,
+ * same member) have finished the previous step: no barrier between members or
+ * steps, so members of different sizes and the end of one step overlap the
+ * start of the next. A step with the periodic check runs stepwise. Members
+ * narrower than block_x get proportionally taller strips under either
+ * schedule, so every tile holds about block_x x rows_per_block nodes. Needs
+ * block_x 128, 256 or 512, strips of at least 3 rows and no lattice-node
+ * members (LB_EINVAL otherwise). Results are identical under both schedules.
+ * spin_limit: polls a waiting workgroup makes before it gives up (0 = the
+ * default, 2^20; a wait also gives up after about one second); when one gives
+ * up, every workgroup leaves and the next synchronising call on the batch
+ * returns LB_EHIP (the state is then invalid).
+ * lb_batch_autotune (and lb_batch_init without a tuning) times both schedules
+ * and keeps the faster. */
+#define LB_SCHEDULE_STEPWISE 0
+#define LB_SCHEDULE_PERSISTENT 1
+int lb_batch_set_schedule(lb_batch* b, int32_t schedule, uint32_t spin_limit);
+int lb_batch_get_schedule(lb_batch* b, int32_t* schedule);
 int lb_batch_get_tuning(lb_batch* b, lb_tuning* t);
 int lb_batch_free(lb_batch* b);
 

@@ -54,6 +54,7 @@ constexpr int kEY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
 constexpr int kGraphSteps = 32;  // longest window of timesteps in one captured graph
 constexpr int kGraphLens = 6;    // windows of 1, 2, 4, ..., 32 steps
 constexpr int kBatchTuneSteps = 4;  // timed steps per candidate when lb_batch_init tunes
+constexpr uint32_t kDefaultSpinLimit = 1u << 20;  // polls before a persistent wait gives up
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -178,6 +179,14 @@ struct Group {
     hipGraphExec_t graph[kGraphLens * 4] = {};
     bool batched = false;
     bool any_walls = false;  // a batch member uses lattice-node bounce-back
+    // persistent schedule of a batch (sweep_persistent_kernel)
+    int schedule = LB_SCHEDULE_STEPWISE;
+    uint32_t spin_limit = kDefaultSpinLimit;
+    Tile* d_ptiles = nullptr;    // tiles in logical order (member-major, row-major)
+    int32_t* d_deps = nullptr;   // kPersistDeps logical tile ids per tile (-1 = none)
+    int32_t* d_sync = nullptr;   // [0] error flag, [1] claim counter, [2..] done per tile
+    int persist_grid = 0;        // workgroups of a persistent launch
+    int max_deps = 0;            // most tiles one tile depends on, current tiling
 };
 
 struct lb_handle {
@@ -445,18 +454,56 @@ int check_tuning(int bx, int rows) {
     return LB_OK;
 }
 
-// Tile table of a batched group for the current tuning.
+// Strip height of batch member `mb` under tuning (bx, rows): a member narrower
+// than bx gets strips taller in proportion, so its tiles hold about as many
+// nodes as the others' (bx x rows); never more than the member's height.
+int member_rows(const lb_params& p, int bx, int rows) {
+    const int64_t widen = p.nx < bx ? (bx + p.nx - 1) / p.nx : 1;
+    return (int)std::min<int64_t>((int64_t)rows * widen, p.ny);
+}
+
+// Tile tables of a batched group for the current tuning: the stepwise table in
+// XCD-aware order, the logical table (member-major, row-major) of the
+// persistent schedule, and each tile's dependencies: the tiles of the same
+// member holding a column and a row that its step reads (itself included).
 int build_tiles(Group& g) {
+    g.max_deps = 0;
     std::vector<Tile> logical;
-    std::vector<int32_t> first;
+    std::vector<int32_t> first, deps;
     for (size_t k = 0; k < g.m.size(); ++k) {
         const lb_params& p = g.m[k].p;
+        const int rows = member_rows(p, g.block_x, g.rows);
         first.push_back((int32_t)logical.size());
         const int tx = (p.nx + g.block_x - 1) / g.block_x;
-        const int ty = (p.ny + g.rows - 1) / g.rows;
+        const int ty = (p.ny + rows - 1) / rows;
+        const int base = (int)logical.size();
         for (int j = 0; j < ty; ++j)
-            for (int i = 0; i < tx; ++i)
-                logical.push_back(Tile{(int32_t)k, i, j, (int32_t)logical.size()});
+            for (int i = 0; i < tx; ++i) {
+                const int y0 = j * rows, y1 = std::min((j + 1) * rows, p.ny);
+                logical.push_back(Tile{(int32_t)k, i, j, (int32_t)logical.size(), y0, y1});
+                // Column and strip indices reached by the tile's step: its pulls
+                // and phi stencil with ghosts reach three nodes beyond its
+                // columns (wrapped lanes included) and rows, periodically.
+                const int x0 = i * g.block_x, x1 = std::min(x0 + g.block_x, p.nx);
+                std::vector<int> cols, strips;
+                for (int c = x0 - 3; c <= x1 + 2; ++c) {
+                    const int ci = ((c % p.nx) + p.nx) % p.nx / g.block_x;
+                    if (std::find(cols.begin(), cols.end(), ci) == cols.end()) cols.push_back(ci);
+                }
+                for (int r = y0 - 3; r <= y1 + 2; ++r) {
+                    const int sj = std::min(((r % p.ny) + p.ny) % p.ny / rows, ty - 1);
+                    if (std::find(strips.begin(), strips.end(), sj) == strips.end())
+                        strips.push_back(sj);
+                }
+                int nd = 0;
+                for (int sj : strips)
+                    for (int ci : cols) {
+                        if (nd < kPersistDeps) deps.push_back(base + sj * tx + ci);
+                        ++nd;
+                    }
+                for (int q = nd; q < kPersistDeps; ++q) deps.push_back(-1);
+                g.max_deps = std::max(g.max_deps, nd);
+            }
     }
     first.push_back((int32_t)logical.size());
     // Workgroup b takes logical tile xcd_tile(b, n): members' neighbouring
@@ -468,17 +515,75 @@ int build_tiles(Group& g) {
         return fail(LB_EINVAL, "tile table too small for this tuning");
     HIPCHK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.d_ptiles, logical.data(), logical.size() * sizeof(Tile),
+                          hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.d_deps, deps.data(), deps.size() * 4, hipMemcpyHostToDevice,
+                          g.stream));
     HIPCHK(hipMemcpyAsync(g.d_first, first.data(), first.size() * 4, hipMemcpyHostToDevice,
                           g.stream));
     HIPCHK(hipStreamSynchronize(g.stream));
     return LB_OK;
 }
 
+// Whether the batch can run the persistent schedule with its tuning: a tile's
+// reach (three nodes) must stay within its neighbouring tiles.
+bool persistent_ok(const Group& g, std::string* why) {
+    if (g.any_walls) {
+        if (why) *why = "lattice-node bounce-back members need the stepwise schedule";
+        return false;
+    }
+    if (g.block_x != 128 && g.block_x != 256 && g.block_x != 512) {
+        if (why) *why = "the persistent schedule takes block_x 128, 256 or 512";
+        return false;
+    }
+    for (const auto& mb : g.m) {
+        const int rows = member_rows(mb.p, g.block_x, g.rows);
+        if (rows < 3 && rows < mb.p.ny) {
+            if (why) *why = "the persistent schedule needs strips of at least 3 rows";
+            return false;
+        }
+    }
+    if (g.max_deps > kPersistDeps) {
+        if (why) *why = "a tile of this tiling depends on more tiles than the persistent "
+                        "schedule tracks";
+        return false;
+    }
+    return true;
+}
+
+// Workgroups of a persistent launch: as many as fit on the device at once.
+int persistent_grid(Group& g) {
+    int dev = 0, cus = 0, per_cu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const lb_params& p = g.m[0].p;
+    HIPCHK(persistent_occupancy(p.storage, p.collision, g.block_x, p.tau_phi == 1.0, &per_cu));
+    g.persist_grid = std::max(1, cus * std::max(1, per_cu));
+    return LB_OK;
+}
+
 int current_tiles(const Group& g) {
     int n = 0;
-    for (const auto& mb : g.m)
-        n += ((mb.p.nx + g.block_x - 1) / g.block_x) * ((mb.p.ny + g.rows - 1) / g.rows);
+    for (const auto& mb : g.m) {
+        const int rows = g.batched ? member_rows(mb.p, g.block_x, g.rows) : g.rows;
+        n += ((mb.p.nx + g.block_x - 1) / g.block_x) * ((mb.p.ny + rows - 1) / rows);
+    }
     return n;
+}
+
+// Enqueue `len` timesteps of a batch on the persistent schedule, starting at
+// `parity`: clear the claim counter and the per-tile step counts, then one
+// persistent launch.
+hipError_t enqueue_persistent(Group& g, int len, int parity, hipStream_t st) {
+    const Member& m0 = g.m[0];
+    const int nt = current_tiles(g);
+    hipError_t e = launch_fill(g.d_sync + 1, 0, (size_t)(nt + 1) * 4, st);
+    if (e != hipSuccess) return e;
+    const int grid = (int)std::min<int64_t>(g.persist_grid, (int64_t)nt * len);
+    return launch_persistent(m0.p.storage, m0.p.collision, g.block_x, m0.p.tau_phi == 1.0,
+                             g.d_views, g.d_ptiles, g.d_deps, nt, len, parity, grid, g.d_sync + 2,
+                             reinterpret_cast<uint32_t*>(g.d_sync + 1), g.d_sync, g.spin_limit,
+                             st);
 }
 
 // Enqueue one timestep of every member on stream st.
@@ -517,6 +622,26 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
                            g.d_flag, st);
 }
 
+// Enqueue `len` timesteps starting at `parity`, the first with the periodic
+// check when `check`: one launch per step, or, for a batch on the persistent
+// schedule, the checked step (if any) and then one persistent launch.
+hipError_t enqueue_window(Group& g, int len, int parity, bool check, hipStream_t st) {
+    if (g.batched && g.schedule == LB_SCHEDULE_PERSISTENT) {
+        int done = 0;
+        if (check) {
+            hipError_t e = enqueue_one(g, true, parity, st);
+            if (e != hipSuccess) return e;
+            done = 1;
+        }
+        if (done < len) return enqueue_persistent(g, len - done, (parity + done) & 1, st);
+        return hipSuccess;
+    }
+    hipError_t ce = hipSuccess;
+    for (int s = 0; s < len && ce == hipSuccess; ++s)
+        ce = enqueue_one(g, check && s == 0, (parity + s) & 1, st);
+    return ce;
+}
+
 // Capture `len` timesteps starting at `parity`, the first with the periodic
 // check when `check`, into one executable graph.
 int capture_graph(Group& g, int len, int parity, bool check, hipGraphExec_t* out) {
@@ -524,9 +649,7 @@ int capture_graph(Group& g, int len, int parity, bool check, hipGraphExec_t* out
     if (!g.capture_stream)
         HIPCHK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
-    hipError_t ce = hipSuccess;
-    for (int s = 0; s < len && ce == hipSuccess; ++s)
-        ce = enqueue_one(g, check && s == 0, (parity + s) & 1, g.capture_stream);
+    hipError_t ce = enqueue_window(g, len, parity, check, g.capture_stream);
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(g.capture_stream, &graph);
     if (ce != hipSuccess || ee != hipSuccess) {
@@ -587,6 +710,14 @@ int group_step(Group& g, int64_t nsteps) {
 }
 
 int check_flag(Group& g) {
+    if (g.batched && g.d_sync) {
+        int32_t err = 0;
+        HIPCHK(hipMemcpyAsync(&err, g.d_sync, 4, hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        if (err)
+            return fail(LB_EHIP, "persistent schedule: a wait for a neighbouring tile exceeded "
+                                 "its poll limit; the state is not valid");
+    }
     for (size_t k = 0; k < g.m.size(); ++k) {
         int32_t flag = 0;
         const int32_t* src = g.batched ? g.d_flag + k
@@ -848,11 +979,37 @@ int set_tuning(Group& g, int bx, int rows) {
             return fail(LB_EINVAL, "tuning needs more tiles than were allocated");
         }
         destroy_graphs(g);
-        return build_tiles(g);
+        int rc2 = build_tiles(g);
+        if (rc2) return rc2;
+        if (g.schedule == LB_SCHEDULE_PERSISTENT) {
+            std::string why;
+            if (!persistent_ok(g, &why)) {
+                g.block_x = old_bx;
+                g.rows = old_rows;
+                rc2 = build_tiles(g);
+                return rc2 ? rc2 : fail(LB_EINVAL, why);
+            }
+            rc2 = persistent_grid(g);
+        }
+        return rc2;
     }
     g.block_x = bx;
     g.rows = rows;
     destroy_graphs(g);
+    return LB_OK;
+}
+
+int set_schedule(Group& g, int schedule) {
+    if (schedule != LB_SCHEDULE_STEPWISE && schedule != LB_SCHEDULE_PERSISTENT)
+        return fail(LB_EINVAL, "schedule must be LB_SCHEDULE_STEPWISE or LB_SCHEDULE_PERSISTENT");
+    if (schedule == LB_SCHEDULE_PERSISTENT) {
+        std::string why;
+        if (!persistent_ok(g, &why)) return fail(LB_EINVAL, why);
+        int rc = persistent_grid(g);
+        if (rc) return rc;
+    }
+    if (schedule != g.schedule) destroy_graphs(g);
+    g.schedule = schedule;
     return LB_OK;
 }
 
@@ -863,7 +1020,7 @@ std::mutex g_tune_mu;
 // instance, lattice-node bounce-back adds the wall launch and the tau table
 // changes the per-node arithmetic.
 using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int, int, int>;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+std::map<TuneKey, std::tuple<int, int, int>> g_tune_cache;  // block_x, rows, schedule
 
 int autotune(Group& g, int steps, lb_tuning* chosen) {
     Range range("lb autotune");
@@ -886,14 +1043,23 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            int rc = set_tuning(g, it->second.first, it->second.second);
+            int rc = set_schedule(g, LB_SCHEDULE_STEPWISE);
+            if (!rc) rc = set_tuning(g, std::get<0>(it->second), std::get<1>(it->second));
+            if (!rc) rc = set_schedule(g, std::get<2>(it->second));
             if (chosen) *chosen = lb_tuning{g.block_x, g.rows};
             return rc;
         }
     }
-    const int cand_bx[] = {64, 128, 256, 512, 1024};
-    const int cand_rows[] = {8, 16, 32, 64, 128};
-    int best_bx = g.block_x, best_rows = g.rows;
+    // Candidates: (schedule, block_x, rows). Batches also try the persistent
+    // schedule, with the strip heights scaled per member (member_rows).
+    std::vector<std::tuple<int, int, int>> cands;
+    for (int bx : {64, 128, 256, 512, 1024})
+        for (int rows : {8, 16, 32, 64, 128}) cands.emplace_back(LB_SCHEDULE_STEPWISE, bx, rows);
+    if (g.batched)
+        for (int bx : {128, 256, 512})
+            for (int rows : {4, 8, 16, 32}) cands.emplace_back(LB_SCHEDULE_PERSISTENT, bx, rows);
+    const int sched_save = g.schedule;
+    int best_bx = g.block_x, best_rows = g.rows, best_sched = g.schedule;
     float best = 1e30f;
     const int diag_save = g.m[0].p.diag_every;
     // Destroys the timing events on every return path of the trial loop.
@@ -910,30 +1076,40 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
         HIPCHK(hipEventCreate(&ev.e0));
         HIPCHK(hipEventCreate(&ev.e1));
         hipEvent_t e0 = ev.e0, e1 = ev.e1;
-        for (int bx : cand_bx)
-            for (int rows : cand_rows) {
-                if (rows > 2 * max_ny) continue;
-                if (set_tuning(g, bx, rows)) continue;
-                for (int s = 0; s < 2; ++s)
-                    HIPCHK(enqueue_one(g, false, (g.parity + s) & 1, g.stream));
-                HIPCHK(hipEventRecord(e0, g.stream));
-                for (int s = 0; s < steps; ++s)
-                    HIPCHK(enqueue_one(g, false, (g.parity + s) & 1, g.stream));
-                HIPCHK(hipEventRecord(e1, g.stream));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; best_bx = bx; best_rows = rows; }
+        for (const auto& c : cands) {
+            const int sched = std::get<0>(c), bx = std::get<1>(c), rows = std::get<2>(c);
+            if (rows > 2 * max_ny) continue;
+            if (set_schedule(g, LB_SCHEDULE_STEPWISE) || set_tuning(g, bx, rows) ||
+                set_schedule(g, sched))
+                continue;
+            HIPCHK(enqueue_window(g, 2, g.parity, false, g.stream));
+            HIPCHK(hipEventRecord(e0, g.stream));
+            HIPCHK(enqueue_window(g, steps, g.parity, false, g.stream));
+            HIPCHK(hipEventRecord(e1, g.stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_bx = bx;
+                best_rows = rows;
+                best_sched = sched;
             }
+        }
         return LB_OK;
     });
     for (auto& mb : g.m) mb.p.diag_every = diag_save;
-    if (rc) return rc;
-    rc = set_tuning(g, best_bx, best_rows);
+    if (rc) {
+        (void)set_schedule(g, sched_save);
+        return rc;
+    }
+    rc = set_schedule(g, LB_SCHEDULE_STEPWISE);
+    if (!rc) rc = set_tuning(g, best_bx, best_rows);
+    if (!rc) rc = set_schedule(g, best_sched);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = {best_bx, best_rows};
+        g_tune_cache[key] = std::make_tuple(best_bx, best_rows, best_sched);
     }
     if (chosen) *chosen = lb_tuning{g.block_x, g.rows};
     return LB_OK;
@@ -1332,7 +1508,10 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
     const size_t off_diag = off_part + round_up(tiles_max * kPartials * 8, 256);
     const size_t off_flag = off_diag + round_up((size_t)n * kPartials * 8, 256);
     const size_t off_views = off_flag + round_up((size_t)n * 4, 256);
-    const size_t bytes = off_views + round_up((size_t)n * sizeof(View), 256);
+    const size_t off_ptiles = off_views + round_up((size_t)n * sizeof(View), 256);
+    const size_t off_deps = off_ptiles + round_up(tiles_max * sizeof(Tile), 256);
+    const size_t off_sync = off_deps + round_up(tiles_max * kPersistDeps * 4, 256);
+    const size_t bytes = off_sync + round_up((tiles_max + 2) * 4, 256);
     hipError_t e = hipMalloc(&g.batch_alloc, bytes);
     if (e != hipSuccess) {
         g.batch_alloc = nullptr;
@@ -1346,6 +1525,9 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
     g.d_diag = reinterpret_cast<double*>(base + off_diag);
     g.d_flag = reinterpret_cast<int32_t*>(base + off_flag);
     g.d_views = reinterpret_cast<View*>(base + off_views);
+    g.d_ptiles = reinterpret_cast<Tile*>(base + off_ptiles);
+    g.d_deps = reinterpret_cast<int32_t*>(base + off_deps);
+    g.d_sync = reinterpret_cast<int32_t*>(base + off_sync);
     int rc = LB_OK;
     if (launch_fill(base + off_tiles, 0, bytes - off_tiles, g.stream) != hipSuccess)
         rc = fail(LB_EHIP, "fill failed");
@@ -1411,6 +1593,22 @@ int lb_batch_contact_angle(lb_batch* b, int32_t k, double x_lo, double x_hi, dou
 int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen) {
     if (!b) return fail(LB_EINVAL, "batch is NULL");
     return autotune(b->g, steps_per_trial, chosen);
+}
+
+int lb_batch_set_schedule(lb_batch* b, int32_t schedule, uint32_t spin_limit) {
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->g.stream));
+    int rc = set_schedule(b->g, schedule);
+    if (rc) return rc;
+    b->g.spin_limit = spin_limit ? spin_limit : kDefaultSpinLimit;
+    destroy_graphs(b->g);  // the poll limit is a launch argument
+    return LB_OK;
+}
+
+int lb_batch_get_schedule(lb_batch* b, int32_t* schedule) {
+    if (!b || !schedule) return fail(LB_EINVAL, "NULL argument");
+    *schedule = b->g.schedule;
+    return LB_OK;
 }
 
 int lb_batch_get_tuning(lb_batch* b, lb_tuning* t) {

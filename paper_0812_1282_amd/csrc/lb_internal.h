@@ -77,7 +77,8 @@ struct View {
 
 struct Tile {
     int32_t member, tx, ty;
-    int32_t id;  // logical tile index (member-major, row-major): its partial-sum record
+    int32_t id;      // logical tile index (member-major, row-major): its partial-sum record
+    int32_t y0, y1;  // rows y0 .. y1-1 of the member (strip heights may differ per member)
 };
 
 // XCD-aware order of workgroups: the device hands consecutive workgroup ids to
@@ -112,6 +113,19 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
                         bool inplace, const View* d_views, const Tile* d_tiles, int n_blocks_1d,
                         int grid_x, int grid_y, int rows, int parity, double* partials,
                         hipStream_t stream);
+// Persistent window of `steps` timesteps of a batch (sweep_persistent_kernel):
+// `grid` workgroups claim (step, tile) items from *next in step-major order and
+// wait on done[] for the tiles listed in d_deps (kPersistDeps per tile, -1 =
+// none). done[] and *next must be zero at the start; *err is set when a wait
+// exceeds spin_limit polls. block_x 128, 256 or 512; no periodic check.
+constexpr int kPersistDeps = 16;
+hipError_t launch_persistent(int storage, int collision, int block_x, bool tau_phi_one,
+                             const View* d_views, const Tile* d_tiles, const int32_t* d_deps,
+                             int n_tiles, int steps, int parity0, int grid, int32_t* done,
+                             uint32_t* next, int32_t* err, uint32_t spin_limit,
+                             hipStream_t stream);
+hipError_t persistent_occupancy(int storage, int collision, int block_x, bool tau_phi_one,
+                                int* per_cu);
 // Lattice-node bounce-back: the wall nodes' reversal for one step, over the
 // same tiles as the sweep (members whose bounce is 0 are skipped).
 hipError_t launch_walls(int storage, int block_x, const View* d_views, const Tile* d_tiles,

@@ -526,10 +526,15 @@ constexpr int kWaves = (S == ST_F64 || S == ST_F64C)
 // columns, the wrapped columns of idle lanes) comes from the band plane that
 // the pre-pass of this step wrote, since their slots may already hold the
 // populations of the next step.
+//
+// sweep_tile is one workgroup's share of a step: columns tx*BX .. tx*BX+BX-1 and
+// rows y0 .. y1-1 of lattice `member`, strip index ty (odd strips walk
+// downwards), read from buf[parity], written to the other buffer; tile_id is
+// its partial-sum record.
 template <int S, int COLL, int BX, bool DIAG, bool G1, int M>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
-void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles, int rows,
-                  int grid_x, int parity, double* __restrict__ partials) {
+__device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int member, int tx,
+                                           int ty, int ty0, int ty1, int tile_id, int parity,
+                                           double* __restrict__ partials) {
     using F = Fmt<S>;
     using real = typename F::real;
     constexpr int W = BX + 4;
@@ -540,18 +545,6 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     constexpr int kGS = F::gstate ? 4 : 1, kGW = F::gstate ? BX + 6 : 1;
     __shared__ SW sst[kGS][4][kGW];
 
-    int member = 0, tx, ty, tile_id;
-    if (tiles) {  // batched members: the table is already in XCD-aware order
-        const Tile tl = tiles[blockIdx.x];
-        member = tl.member;
-        tx = tl.tx;
-        ty = tl.ty;
-        tile_id = tl.id;
-    } else {
-        tile_id = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-        tx = tile_id % grid_x;
-        ty = tile_id / grid_x;
-    }
     const View v = views[member];  // uniform: lives in scalar registers
     const int nx = v.nx, ny = v.ny;
     // ?: rather than indexing buf[] by a runtime value (which would put the
@@ -568,18 +561,26 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
         return m;
     };
     const int x0 = tx * BX;
-    const int y0 = ty * rows;
-    const int y1 = min(y0 + rows, ny);
+    const int y0 = ty0;
+    const int y1 = min(ty1, ny);
     const int d = (ty & 1) ? -1 : 1;  // walking direction of this strip
     const bool active = x0 + t < nx;
+    // Lanes past the right edge hold wrapped columns; only the first two of
+    // them (lanes nx - x0 and nx - x0 + 1) are read, by the stencil and the
+    // ghost values of the last active columns, so the others skip their pulls
+    // (narrow lattices on wide tiles).
+    const bool used = x0 + t <= nx + 1;
     // Lanes past the right edge compute phi of the wrapped columns the
     // stencil of the last active columns needs.
     const uint32_t x = (uint32_t)((x0 + t) % nx);
     const uint32_t xm = x == 0 ? nx - 1 : x - 1;
     const uint32_t xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
     // Threads 0..3 also compute phi of the halo columns x0-2, x0-1, x0+BX,
-    // x0+BX+1. (Spreading these over the wavefronts measured slower.)
-    const bool halo = t < 4;
+    // x0+BX+1. The stencil and ghost values of the active columns read up to
+    // column nx + 1, so in a partial tile the right pair is skipped where it
+    // lies beyond that (the wrapped lanes hold those columns). (Spreading
+    // these over the wavefronts measured slower.)
+    const bool halo = t < 2 || (t < 4 && x0 + BX + t - 2 <= nx + 1);
     const int hcol = t < 2 ? t : BX + t;
     const uint32_t hx = (uint32_t)(((x0 - 2 + hcol) % nx + nx) % nx);
     const uint32_t hxm = hx == 0 ? nx - 1 : hx - 1;
@@ -640,7 +641,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                 sst[yy & 3][2][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<11>(v));
                 sst[yy & 3][3][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<12>(v));
             };
-            ld(x, t + 3);
+            if (x0 + t <= nx + 2) ld(x, t + 3);  // the state columns the used lanes read
             if (shalo) ld(sx, scol);
         }
     };
@@ -723,6 +724,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             return;
         }
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        if (!used) nb = 0xFFu;
         sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
         if (halo) {
             real hg[9], hf[9], hs, hb;
@@ -742,7 +744,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
             const int y = wrap(yy, ny);
             const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
-            rawNbM = nrow[x];
+            rawNbM = used ? nrow[x] : 0xFFu;
             if (rawNbM != 0xFFu) pairs_issue<S>(R, v, co, rawM);
             if (halo) {
                 rawNbH = nrow[hx];
@@ -1224,6 +1226,118 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
     }
 }
 
+// One step: workgroup b sweeps one tile. A single lattice takes logical tile
+// xcd_tile(b, n) of its (grid_x x strips) tiling; a batch reads its tile table
+// (already in XCD-aware order).
+template <int S, int COLL, int BX, bool DIAG, bool G1, int M>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
+void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles, int rows,
+                  int grid_x, int parity, double* __restrict__ partials) {
+    if (tiles) {
+        const Tile tl = tiles[blockIdx.x];
+        sweep_tile<S, COLL, BX, DIAG, G1, M>(views, tl.member, tl.tx, tl.ty, tl.y0, tl.y1, tl.id,
+                                             parity, partials);
+    } else {
+        const int tile_id = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+        const int tx = tile_id % grid_x, ty = tile_id / grid_x;
+        sweep_tile<S, COLL, BX, DIAG, G1, M>(views, 0, tx, ty, ty * rows, ty * rows + rows,
+                                             tile_id, parity, partials);
+    }
+}
+
+// Persistent form of a window of `steps` timesteps of a batch: each workgroup
+// takes work items in order from a counter, item i being tile i % n of step
+// i / n (step-major, the tiles of a step in the table's order), and sweeps it
+// once the tiles it depends on have finished the previous step. A tile's step
+// reads the previous step's populations of its own tile and of the tiles
+// holding nodes within three of it (the pulls and the phi stencil with its
+// ghosts), and overwrites the buffer those tiles read in the previous step, so
+// both hazards are covered by the same condition: done[d] >= step for every d
+// listed in deps (kPersistDeps entries per tile, -1 = none, the tile itself
+// included). There is no barrier between members or between steps.
+//
+// Progress: items are claimed in order and each depends only on items of the
+// previous step, all claimed earlier by running workgroups, so the unfinished
+// item of lowest step can always proceed; no workgroup waits on one that has
+// not started. Every wait is bounded: after spin_limit polls or about one
+// second (or once another workgroup has reported a timeout) the workgroup sets
+// *err and leaves, so the grid always drains; the host reports the error.
+//
+// Memory ordering: a tile's populations are written by all its threads; each
+// wave waits for its stores to complete before the barrier, after which thread
+// 0 makes them visible device-wide (other XCDs included) with one agent-scope
+// release fence and publishes the step with an atomic store. A waiting
+// thread polls done[] with relaxed agent-scope loads and then issues one
+// agent-scope acquire fence; the barrier that follows orders the tile's pulls
+// after it.
+constexpr uint64_t kWaitTicks = 100000000;  // one second of the 100 MHz wall clock
+template <int S, int COLL, int BX, bool G1>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
+void sweep_persistent_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles,
+                             const int32_t* __restrict__ deps, int n_tiles, int steps,
+                             int parity0, int32_t* done, uint32_t* next, int32_t* err,
+                             uint32_t spin_limit) {
+    __shared__ int s_item, s_abort;
+    const int t = threadIdx.x;
+    const int total = n_tiles * steps;
+    // Thread 0 publishes the previous item's step (after the barrier that ends
+    // it) in the same block as the next claim, so each iteration has one
+    // thread-0 block at its top, then barriers and branches that are uniform.
+    int prev_j = -1, prev_k = 0;
+    for (;;) {
+        if (t == 0) {
+            // relaxed: thread 0's release fence at the end of the item orders it
+            if (prev_j >= 0)
+                __hip_atomic_store(done + prev_j, prev_k + 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_item = (int)atomicAdd(next, 1u);
+            s_abort = 0;
+        }
+        __syncthreads();
+        // Uniform values read through readfirstlane, so that the compiler
+        // treats the loop exits as uniform.
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= total) break;
+        const int k = item / n_tiles, j = item - k * n_tiles;
+        if (t < kPersistDeps) {
+            const int d = deps[(int64_t)j * kPersistDeps + t];
+            if (d >= 0 &&
+                __hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                // Poll with relaxed loads (no cache invalidation per poll); the
+                // acquire fence after the loop orders the tile's reads. Bounded
+                // by spin_limit polls and by about one second of wall clock.
+                const uint64_t t0 = (uint64_t)wall_clock64();
+                uint32_t polls = 0;
+                while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                    if (++polls > spin_limit || (uint64_t)wall_clock64() - t0 > kWaitTicks ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        s_abort = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(s_abort)) break;
+        const Tile tl = tiles[j];
+        sweep_tile<S, COLL, BX, false, G1, 0>(views, tl.member, tl.tx, tl.ty, tl.y0, tl.y1, tl.id,
+                                              (parity0 + k) & 1, nullptr);
+        // Every wave waits until its stores have completed (reached L2), then
+        // the barrier; thread 0's agent-scope release (one L2 write-back for the
+        // workgroup) then covers the whole tile when it publishes the step.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        prev_j = j;
+        prev_k = k;
+    }
+    if (t == 0 && prev_j >= 0)
+        __hip_atomic_store(done + prev_j, prev_k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // In-place pre-pass: phi of S_n at the tile-border nodes, into View::band,
 // with the arithmetic of the sweep's own phi (the same pulls summed in the same
 // order, so the sweep obtains the same bits either way). The nodes are the rows
@@ -1298,15 +1412,17 @@ template <int S>
 __global__ __launch_bounds__(1024) void wall_kernel(const View* __restrict__ views,
                                                    const Tile* __restrict__ tiles, int rows,
                                                    int grid_x, int parity) {
-    int member = 0, tx, ty;
+    int member = 0, tx, y0, y1;
     if (tiles) {
         const Tile tl = tiles[blockIdx.x];
         member = tl.member;
         tx = tl.tx;
-        ty = tl.ty;
+        y0 = tl.y0;
+        y1 = tl.y1;
     } else {
         tx = (int)blockIdx.x % grid_x;
-        ty = (int)blockIdx.x / grid_x;
+        y0 = ((int)blockIdx.x / grid_x) * rows;
+        y1 = y0 + rows;
     }
     const View v = views[member];
     if (!v.bounce) return;
@@ -1317,7 +1433,7 @@ __global__ __launch_bounds__(1024) void wall_kernel(const View* __restrict__ vie
     char* dst = parity ? v.buf[0] : v.buf[1];
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const ColOff co = col_offsets<S>((uint32_t)x, xm, xp);
-    const int y0 = ty * rows, y1 = min(y0 + rows, ny);
+    y1 = min(y1, ny);
     for (int y = y0; y < y1; ++y) {
         const size_t node = (size_t)y * v.pitch + x;
         if (v.nbr[node] != 0xFFu) continue;
@@ -1397,6 +1513,70 @@ static hipError_t sweep_b(const SweepArgs& a) {
     }
 }
 
+struct PersistArgs {
+    int collision, block_x;
+    bool tau_phi_one;
+    const View* views;
+    const Tile* tiles;
+    const int32_t* deps;
+    int n_tiles, steps, parity0, grid;
+    int32_t* done;
+    uint32_t* next;
+    int32_t* err;
+    uint32_t spin_limit;
+    hipStream_t stream;
+};
+
+template <int S, int C, int BX>
+static hipError_t persist_g(const PersistArgs& a) {
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(a.grid), dim3(BX), 0, a.stream, a.views, a.tiles, a.deps,
+                           a.n_tiles, a.steps, a.parity0, a.done, a.next, a.err, a.spin_limit);
+    };
+    if (Fmt<S>::gstate || a.tau_phi_one) go(sweep_persistent_kernel<S, C, BX, true>);
+    else if constexpr (!Fmt<S>::gstate) go(sweep_persistent_kernel<S, C, BX, false>);
+    return hipGetLastError();
+}
+
+template <int S, int C>
+static hipError_t persist_b(const PersistArgs& a) {
+    switch (a.block_x) {
+        case 128: return persist_g<S, C, 128>(a);
+        case 256: return persist_g<S, C, 256>(a);
+        case 512: return persist_g<S, C, 512>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+hipError_t persist_fmt(const PersistArgs& a) {
+    return a.collision == CO_MRT ? persist_b<S, CO_MRT>(a) : persist_b<S, CO_BGK>(a);
+}
+
+// Workgroups of the persistent kernel that fit on the device at once.
+template <int S>
+hipError_t persist_occupancy(int block_x, int collision, bool tau_phi_one, int* per_cu) {
+    hipError_t e = hipErrorInvalidValue;
+    auto occ = [&](auto kernel, int bx) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, bx, 0);
+    };
+    const bool g1 = Fmt<S>::gstate || tau_phi_one;
+#define LB_OCC(C, BX)                                                                   \
+    if (g1) occ(sweep_persistent_kernel<S, C, BX, true>, BX);                           \
+    else if constexpr (!Fmt<S>::gstate) occ(sweep_persistent_kernel<S, C, BX, false>, BX);
+    if (collision == CO_MRT) {
+        if (block_x == 128) { LB_OCC(CO_MRT, 128) }
+        else if (block_x == 256) { LB_OCC(CO_MRT, 256) }
+        else if (block_x == 512) { LB_OCC(CO_MRT, 512) }
+    } else {
+        if (block_x == 128) { LB_OCC(CO_BGK, 128) }
+        else if (block_x == 256) { LB_OCC(CO_BGK, 256) }
+        else if (block_x == 512) { LB_OCC(CO_BGK, 512) }
+    }
+#undef LB_OCC
+    return e;
+}
+
 template <int S>
 hipError_t sweep_fmt(const SweepArgs& a) {
     if (a.inplace && (a.tiles || (S != ST_F64 && S != ST_F32))) return hipErrorInvalidValue;
@@ -1439,11 +1619,15 @@ hipError_t wall_fmt(const SweepArgs& a) {
 
 #ifdef LB_SWEEP_UNIT
 template hipError_t sweep_fmt<LB_SWEEP_UNIT>(const SweepArgs&);
+template hipError_t persist_fmt<LB_SWEEP_UNIT>(const PersistArgs&);
+template hipError_t persist_occupancy<LB_SWEEP_UNIT>(int, int, bool, int*);
 template hipError_t wall_fmt<LB_SWEEP_UNIT>(const SweepArgs&);
 template hipError_t band_fmt<LB_SWEEP_UNIT>(bool, int, dim3, const View*, BandArgs, hipStream_t);
 #else
 #define LB_EXTERN_FMT(S)                                                                   \
     extern template hipError_t sweep_fmt<S>(const SweepArgs&);                             \
+    extern template hipError_t persist_fmt<S>(const PersistArgs&);                         \
+    extern template hipError_t persist_occupancy<S>(int, int, bool, int*);                 \
     extern template hipError_t wall_fmt<S>(const SweepArgs&);                              \
     extern template hipError_t band_fmt<S>(bool, int, dim3, const View*, BandArgs, hipStream_t);
 LB_EXTERN_FMT(ST_F64)
@@ -1467,6 +1651,39 @@ hipError_t launch_sweep(int storage, int collision, int block_x, bool diag, bool
         case ST_BF16S: return sweep_fmt<ST_BF16S>(a);
         case ST_F64C: return sweep_fmt<ST_F64C>(a);
         case ST_F32C: return sweep_fmt<ST_F32C>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_persistent(int storage, int collision, int block_x, bool tau_phi_one,
+                             const View* d_views, const Tile* d_tiles, const int32_t* d_deps,
+                             int n_tiles, int steps, int parity0, int grid, int32_t* done,
+                             uint32_t* next, int32_t* err, uint32_t spin_limit,
+                             hipStream_t stream) {
+    if (n_tiles < 1 || steps < 1 || grid < 1 || (int64_t)n_tiles * steps >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    const PersistArgs a{collision, block_x, tau_phi_one, d_views, d_tiles, d_deps, n_tiles,
+                        steps, parity0, grid, done, next, err, spin_limit, stream};
+    switch (storage) {
+        case ST_F64: return persist_fmt<ST_F64>(a);
+        case ST_F32: return persist_fmt<ST_F32>(a);
+        case ST_F16S: return persist_fmt<ST_F16S>(a);
+        case ST_BF16S: return persist_fmt<ST_BF16S>(a);
+        case ST_F64C: return persist_fmt<ST_F64C>(a);
+        case ST_F32C: return persist_fmt<ST_F32C>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t persistent_occupancy(int storage, int collision, int block_x, bool tau_phi_one,
+                                int* per_cu) {
+    switch (storage) {
+        case ST_F64: return persist_occupancy<ST_F64>(block_x, collision, tau_phi_one, per_cu);
+        case ST_F32: return persist_occupancy<ST_F32>(block_x, collision, tau_phi_one, per_cu);
+        case ST_F16S: return persist_occupancy<ST_F16S>(block_x, collision, tau_phi_one, per_cu);
+        case ST_BF16S: return persist_occupancy<ST_BF16S>(block_x, collision, tau_phi_one, per_cu);
+        case ST_F64C: return persist_occupancy<ST_F64C>(block_x, collision, tau_phi_one, per_cu);
+        case ST_F32C: return persist_occupancy<ST_F32C>(block_x, collision, tau_phi_one, per_cu);
         default: return hipErrorInvalidValue;
     }
 }

@@ -381,6 +381,75 @@ def fig2(ramp_steps=1_000_000, equil=30_000, n_updates=1000, every=10_000):
     return out
 
 
+def _fig5_batch(torch, params, members, geos, steps, every, label):
+    """Advance one batch of Fig. 5 capillaries and record, every `every` steps,
+    the column length, the centreline meniscus and the advancing angle at the
+    bottom channel wall; fit cos(theta_a) against Ca and l^2 against t."""
+    b = lbm.lb_batch_init(params, members)
+    rec = [[] for _ in members]
+    done, t_run = 0, 0.0
+    alive = [True] * len(members)
+    while done < steps:
+        t_run += _timed(torch, lambda: lbm.lb_batch_step(b, every))
+        done += every
+        for k, g in enumerate(geos):
+            if not alive[k]:
+                continue
+            phi = lbm.lb_batch_read_fields(b, k)[0]
+            if not np.all(np.isfinite(phi)):
+                alive[k] = False
+                rec[k].append((done, None, None, None))
+                continue
+            sol = members[k]["solid"]
+            ch = slice(g["x_in"], g["x_out"])
+            l = (0.5 * (1 + phi[:, ch]))[sol[:, ch] == 0].sum() / g["h"]
+            xm = _meniscus_x(phi, g["x_in"] - 40, g["x_out"], (g["y_lo"] + g["y_hi"]) // 2)
+            th = None
+            if xm is not None and g["x_in"] + 40 < xm < g["x_out"] - 40:
+                try:
+                    th = lbm.lb_batch_contact_angle(b, k, xm - 30.0, xm + 30.0,
+                                                    g["y_lo"] + 3.0, g["y_hi"] - 4.0,
+                                                    g["y_lo"] - 0.5, 1)
+                except lbm.LbError:
+                    th = None
+            rec[k].append((done, float(l), xm, th))
+        if done % (20 * every) == 0:
+            print(f"fig5 {label} step {done}: l = "
+                  f"{[round(r[-1][1], 1) if r and r[-1][1] else None for r in rec]}", flush=True)
+    b.close()
+    torch.cuda.empty_cache()
+    mlups = sum(q.nx * q.ny for q in params) * done / t_run / 1e6
+    out = []
+    for k, p in enumerate(params):
+        nu_a = (p.tau_alpha - 0.5) / 3.0
+        gamma = math.sqrt(8 * p.kappa * p.B / 9)
+        r = [x for x in rec[k] if x[1] is not None]
+        t = np.array([x[0] for x in r], float)
+        l = np.array([x[1] for x in r])
+        th = np.array([np.nan if x[3] is None else x[3] for x in r])
+        fit = None
+        if len(l) > 4:
+            v = np.gradient(l, t)
+            ca = v * nu_a / gamma
+            sel = np.isfinite(th) & (ca > 0) & (t >= 0.1 * steps)
+            if sel.sum() >= 5:
+                slope, c0 = np.polyfit(ca[sel], np.cos(np.radians(th[sel])), 1)
+                w_sel = sel & (l > 50)
+                wash = None
+                if w_sel.sum() >= 5:
+                    ws = np.polyfit(t[w_sel], l[w_sel] ** 2, 1)[0]
+                    pred = (gamma * geos[k]["h"] * np.cos(np.radians(np.nanmean(th[w_sel])))
+                            / (3 * nu_a))
+                    wash = {"l2_slope": float(ws), "washburn_pred": float(pred),
+                            "ratio": float(ws / pred)}
+                fit = {"theta_a_ca0": float(np.degrees(np.arccos(np.clip(c0, -1, 1)))),
+                       "dcos_dca": float(slope), "ca_range": [float(ca[sel].min()),
+                                                               float(ca[sel].max())],
+                       "n": int(sel.sum()), "washburn": wash}
+        out.append({"records": rec[k], "fit": fit, "alive": alive[k], "mlups": mlups})
+    return out
+
+
 def fig5(steps=1_000_000, every=5_000, storage="f64", mobilities=(0.05, 0.1, 0.5),
          collisions=("bgk", "mrt")):
     """Sec. VII: the three mobilities advance together (one batch per collision
@@ -402,68 +471,46 @@ def fig5(steps=1_000_000, every=5_000, storage="f64", mobilities=(0.05, 0.1, 0.5
             members.append(inp)
             params.append(lbm.make_params(p, storage))
             geos.append(inp["geometry"])
-        nu_a = (params[0].tau_alpha - 0.5) / 3.0
-        b = lbm.lb_batch_init(params, members)
-        rec = [[] for _ in mobilities]
-        done, t_run = 0, 0.0
-        alive = [True] * len(mobilities)
-        while done < steps:
-            t_run += _timed(torch, lambda: lbm.lb_batch_step(b, every))
-            done += every
-            for k, g in enumerate(geos):
-                if not alive[k]:
-                    continue
-                phi = lbm.lb_batch_read_fields(b, k)[0]
-                if not np.all(np.isfinite(phi)):
-                    alive[k] = False
-                    rec[k].append((done, None, None, None))
-                    continue
-                sol = members[k]["solid"]
-                ch = slice(g["x_in"], g["x_out"])
-                l = (0.5 * (1 + phi[:, ch]))[sol[:, ch] == 0].sum() / g["h"]
-                xm = _meniscus_x(phi, g["x_in"] - 40, g["x_out"], (g["y_lo"] + g["y_hi"]) // 2)
-                th = None
-                if xm is not None and g["x_in"] + 40 < xm < g["x_out"] - 40:
-                    try:
-                        th = lbm.lb_batch_contact_angle(b, k, xm - 30.0, xm + 30.0,
-                                                        g["y_lo"] + 3.0, g["y_hi"] - 4.0,
-                                                        g["y_lo"] - 0.5, 1)
-                    except lbm.LbError:
-                        th = None
-                rec[k].append((done, float(l), xm, th))
-            if done % (20 * every) == 0:
-                print(f"fig5 {coll} step {done}: l = "
-                      f"{[round(r[-1][1], 1) if r and r[-1][1] else None for r in rec]}", flush=True)
-        b.close()
-        torch.cuda.empty_cache()
-        for k, m in enumerate(mobilities):
-            r = [x for x in rec[k] if x[1] is not None]
-            t = np.array([x[0] for x in r], float)
-            l = np.array([x[1] for x in r])
-            th = np.array([np.nan if x[3] is None else x[3] for x in r])
-            fit = None
-            if len(l) > 4:
-                v = np.gradient(l, t)
-                ca = v * nu_a / gamma
-                sel = np.isfinite(th) & (ca > 0) & (t >= 0.1 * steps)
-                if sel.sum() >= 5:
-                    slope, c0 = np.polyfit(ca[sel], np.cos(np.radians(th[sel])), 1)
-                    w_sel = sel & (l > 50)
-                    wash = None
-                    if w_sel.sum() >= 5:
-                        ws = np.polyfit(t[w_sel], l[w_sel] ** 2, 1)[0]
-                        pred = (gamma * geos[k]["h"] * np.cos(np.radians(np.nanmean(th[w_sel])))
-                                / (3 * nu_a))
-                        wash = {"l2_slope": float(ws), "washburn_pred": float(pred),
-                                "ratio": float(ws / pred)}
-                    fit = {"theta_a_ca0": float(np.degrees(np.arccos(np.clip(c0, -1, 1)))),
-                           "dcos_dca": float(slope), "ca_range": [float(ca[sel].min()),
-                                                                   float(ca[sel].max())],
-                           "n": int(sel.sum()), "washburn": wash}
-            out["runs"].append({"collision": coll, "mobility": m, "records": rec[k],
-                                "fit": fit, "alive": alive[k],
-                                "mlups": sum(q.nx * q.ny for q in params) * done / t_run / 1e6})
-            print(f"fig5 {coll} M={m}: {fit}", flush=True)
+        res = _fig5_batch(torch, params, members, geos, steps, every, coll)
+        for m, r in zip(mobilities, res):
+            out["runs"].append(dict(r, collision=coll, mobility=m))
+            print(f"fig5 {coll} M={m}: {r['fit']}", flush=True)
+    return out
+
+
+def fig5_bgk(steps=1_000_000, every=10_000, storage="f32", mobility=0.1):
+    """What moves the BGK advancing angle of Fig. 5 (M = 0.1): the baseline;
+    Step 2 on; phi clamped to [-1, 1] inside Eq. (tau); the tau table of Sec. VI;
+    and a = 0.04, kappa = 0.01 instead of a = kappa = 0.02 (the same gamma =
+    0.0188, half the interface width: the paper states only gamma). MRT is run
+    with the narrower interface too."""
+    torch = _torch()
+    cases = [("bgk", "baseline", {}, {}), ("bgk", "tau clamp", {"tau_clamp": 1}, {}),
+             ("bgk", "tau table", {"tau_lut": 10000}, {}),
+             ("bgk", "a=0.04 kappa=0.01", {}, {"a": 0.04, "kappa": 0.01}),
+             ("bgk", "Step 2", {"step2": 1}, {}),
+             ("mrt", "a=0.04 kappa=0.01", {}, {"a": 0.04, "kappa": 0.01}),
+             ("mrt", "baseline", {}, {})]
+    out = {"workload": f"Fig. 5 capillary, M = {mobility}, variants", "steps": steps, "runs": []}
+    groups = {}
+    for coll, label, over, land in cases:
+        groups.setdefault((coll, over.get("step2", 1 if coll == "mrt" else 0)), []).append(
+            (label, over, land))
+    for (coll, step2), items in groups.items():
+        members, params, geos = [], [], []
+        for label, over, land in items:
+            a, kappa = land.get("a", 0.02), land.get("kappa", 0.02)
+            dphi = lbm.lb_dphi_for_angle(60.0, kappa, -a, a)
+            p, inp = wl.fig5_capillary(mobility, coll, dphi, a=a, kappa=kappa)
+            p = dict(p, **{k: v for k, v in over.items() if k != "step2"})
+            members.append(inp)
+            params.append(lbm.make_params(p, storage, zero_u_feq=step2))
+            geos.append(inp["geometry"])
+        res = _fig5_batch(torch, params, members, geos, steps, every, f"{coll} step2={step2}")
+        for (label, _, _), r in zip(items, res):
+            out["runs"].append(dict(r, collision=coll, variant=label))
+            th = r["fit"]["theta_a_ca0"] if r["fit"] else None
+            print(f"fig5 variant {coll} {label}: theta_a(Ca->0) = {th}", flush=True)
     return out
 
 
@@ -519,12 +566,13 @@ def variants(steps=100_000, angles=(45.0, 60.0, 90.0, 120.0, 135.0), every=20_00
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig5", "variants"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "fig2", "fig5", "fig5_bgk",
+                                      "variants"])
     ap.add_argument("--out", default="")
     ap.add_argument("--steps", type=int, default=0)
     args = ap.parse_args(argv)
     fn = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "fig2": fig2,
-          "fig5": fig5, "variants": variants}[args.which]
+          "fig5": fig5, "fig5_bgk": fig5_bgk, "variants": variants}[args.which]
     if not args.steps:
         res = fn()
     else:

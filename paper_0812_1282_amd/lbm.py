@@ -30,7 +30,9 @@ EXPORTS = [
     "lb_dphi_for_angle", "lb_batch_init", "lb_batch_step", "lb_batch_read_fields",
     "lb_batch_read_populations", "lb_batch_contact_angle", "lb_batch_get_tuning",
     "lb_batch_free", "lb_bandwidth_probe", "lb_batch_autotune", "lb_diagnostics_noalloc",
+    "lb_batch_set_schedule", "lb_batch_get_schedule",
 ]
+STEPWISE, PERSISTENT = 0, 1
 
 
 class LbError(RuntimeError):
@@ -118,6 +120,8 @@ def load_library(path=LIB_PATH):
         "lb_batch_get_tuning": [_VP, ctypes.POINTER(lb_tuning)],
         "lb_batch_autotune": [_VP, ctypes.c_int32, ctypes.POINTER(lb_tuning)],
         "lb_batch_free": [_VP],
+        "lb_batch_set_schedule": [_VP, i32, ctypes.c_uint32],
+        "lb_batch_get_schedule": [_VP, ctypes.POINTER(i32)],
         "lb_bandwidth_probe": [ctypes.c_size_t, i32, _VP, _D],
     }
     for name, args in sig.items():
@@ -413,6 +417,18 @@ def lb_batch_get_tuning(b):
     t = lb_tuning()
     _check(load_library().lb_batch_get_tuning(b._h, ctypes.byref(t)))
     return t.block_x, t.rows_per_block
+
+
+def lb_batch_set_schedule(b, schedule, spin_limit=0):
+    """STEPWISE (one launch per step) or PERSISTENT (one launch per window of
+    steps with per-tile dependencies); spin_limit 0 = the default poll limit."""
+    _check(load_library().lb_batch_set_schedule(b._h, int(schedule), int(spin_limit)))
+
+
+def lb_batch_get_schedule(b):
+    s = ctypes.c_int32()
+    _check(load_library().lb_batch_get_schedule(b._h, ctypes.byref(s)))
+    return s.value
 
 
 def lb_batch_free(b):

@@ -190,7 +190,7 @@ def c5_member(desc, dphi_wall):
     return p, drop_on_wall(p, 0.4 * desc["ny"], desc["nx"] / 2.0, 0.0, desc["seed"], dphi_wall)
 
 
-def fig5_capillary(mobility, collision, dphi_wall, seed=6):
+def fig5_capillary(mobility, collision, dphi_wall, seed=6, a=0.02, kappa=0.02):
     """The capillary-filling geometry of Sec. VII (Fig. 5): a channel of length
     640 and width h = 50 between two 480 x 200 reservoirs, joined through the
     periodic seam so that their pressures are equal. The lattice is 1600 x 200.
@@ -198,10 +198,12 @@ def fig5_capillary(mobility, collision, dphi_wall, seed=6):
     rows 75..124 (wall planes at y = 74.5 and 124.5). phi = +1 (fluid alpha,
     nu = 0.83) in the left reservoir, -1 (fluid beta, nu = 0.03) in the channel
     and the right reservoir. gamma = 0.0188 gives a = kappa = 0.02; the mobility
-    M = Gamma (tau_phi - 1/2) gives Gamma = 2 M at tau_phi = 1."""
+    M = Gamma (tau_phi - 1/2) gives Gamma = 2 M at tau_phi = 1. Other (a, kappa)
+    with 8 kappa a / 9 = gamma^2 give the same tension with another interface
+    width (the paper states gamma only)."""
     nx, ny, x_in, x_out, y_lo, y_hi = 1600, 200, 480, 1120, 75, 125
     p = params(nx, ny, 3 * 0.83 + 0.5, 3 * 0.03 + 0.5, collision,
-               A=-0.02, B=0.02, kappa=0.02, Gamma=2.0 * mobility)
+               A=-a, B=a, kappa=kappa, Gamma=2.0 * mobility)
     solid = np.zeros((ny, nx), dtype=np.uint8)
     solid[:y_lo, x_in:x_out] = 1
     solid[y_hi:, x_in:x_out] = 1

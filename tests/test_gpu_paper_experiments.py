@@ -41,3 +41,27 @@ def test_fig5_mrt_advancing_angle_at_zero_capillary_number():
     # more mobility, more inter-diffusion at the contact line, faster filling
     finals = [run["records"][-1][1] for run in res["runs"]]
     assert np.all(np.diff(finals) > 0)
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "BGK theta_a(Ca -> 0) measured 67.4/67.8/67.7 degrees against the paper's 75/73/72 for "
+    "M = 0.05/0.1/0.5: above MRT (59-60) as the paper finds, but 5-7 degrees below its BGK "
+    "values; the paper does not state a and kappa (only gamma = 0.0188) or its BGK details"))
+def test_fig5_bgk_advancing_angle_at_zero_capillary_number():
+    """The single-relaxation-time column of Fig. 5 (Sec. VII): the advancing
+    angle at Ca -> 0 against the paper's BGK values, within 2.5 degrees. Kept as
+    a strict expected failure with the measured values (see the reason)."""
+    gold = _golden()
+    print("case fig5 BGK f32, M = 0.05, 0.1, 0.5", flush=True)
+    res = experiments.fig5(steps=1_000_000, every=10_000, storage="f32",
+                           mobilities=tuple(sorted(gold)), collisions=("bgk",))
+    ths = {}
+    for run in res["runs"]:
+        m = run["mobility"]
+        assert run["alive"] and run["fit"] is not None
+        ths[m] = run["fit"]["theta_a_ca0"]
+        print(f"  M = {m}: theta_a(Ca -> 0) = {ths[m]:.2f} (paper {gold[m][1]})", flush=True)
+        # above the MRT value the paper states, as it finds
+        assert ths[m] > gold[m][0] + 3.0
+    for m, th in ths.items():
+        assert abs(th - gold[m][1]) <= 2.5
