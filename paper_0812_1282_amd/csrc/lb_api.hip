@@ -911,6 +911,8 @@ void free_group(Group& g) {
     g.batch_alloc = nullptr;
 }
 
+int pick_default_tiling(Group& g);
+
 int init_single(const lb_params* p, const uint8_t* solid, const double* dphi, const double* phi0,
                 const double* rho0, const double* ux0, const double* uy0, void* stream, void* ext,
                 size_t ext_bytes, lb_handle** out) {
@@ -929,6 +931,7 @@ int init_single(const lb_params* p, const uint8_t* solid, const double* dphi, co
     g.rows = 32;
     rc = alloc_group_single(g, p, ext, ext_bytes);
     if (!rc) rc = init_member(g.m[0], p, solid, dphi, phi0, rho0, ux0, uy0, g.stream);
+    if (!rc) rc = pick_default_tiling(g);
     if (rc) {
         const std::string msg = g_err;
         free_group(g);
@@ -1022,6 +1025,51 @@ std::mutex g_tune_mu;
 using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int, int, int>;
 std::map<TuneKey, std::tuple<int, int, int>> g_tune_cache;  // block_x, rows, schedule
 
+TuneKey tune_key(const Group& g, const char* arch) {
+    int max_ny = 0, total = 0, any_bounce = 0, any_lut = 0;
+    for (auto& mb : g.m) {
+        max_ny = std::max(max_ny, mb.p.ny);
+        total += mb.p.nx * mb.p.ny;
+        any_bounce |= mb.p.bounce == LB_LATTICE_NODE;
+        any_lut |= mb.p.tau_lut > 1;
+    }
+    return TuneKey(std::string(arch), g.m[0].p.nx, max_ny, g.m[0].p.storage, g.m[0].p.collision,
+                   g.m[0].p.inplace, g.batched ? total : -1, g.m[0].p.tau_phi == 1.0, any_bounce,
+                   any_lut);
+}
+
+// Tile shape of a new single lattice: the autotuner's earlier choice for the
+// same problem on this device if there is one; otherwise the tallest strips
+// and widest tiles (from 256 x 32 down to 64 x 4) that still give at least one
+// workgroup per CU, so that small lattices spread over the chip.
+int pick_default_tiling(Group& g) {
+    int dev = 0, cus = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(g, prop.gcnArchName));
+        if (it != g_tune_cache.end()) {
+            g.block_x = std::get<0>(it->second);
+            g.rows = std::get<1>(it->second);
+            return LB_OK;
+        }
+    }
+    const int64_t nx = g.m[0].p.nx, ny = g.m[0].p.ny;
+    g.block_x = 64;
+    g.rows = 4;
+    for (int bx : {256, 128, 64})
+        for (int rows : {32, 16, 8, 4})
+            if (((nx + bx - 1) / bx) * ((ny + rows - 1) / rows) >= cus) {
+                g.block_x = bx;
+                g.rows = rows;
+                return LB_OK;
+            }
+    return LB_OK;
+}
+
 int autotune(Group& g, int steps, lb_tuning* chosen) {
     Range range("lb autotune");
     if (steps < 1) return fail(LB_EINVAL, "steps_per_trial must be >= 1");
@@ -1029,16 +1077,9 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipGetDeviceProperties(&prop, dev));
-    int max_ny = 0, total = 0;
-    for (auto& mb : g.m) { max_ny = std::max(max_ny, mb.p.ny); total += mb.p.nx * mb.p.ny; }
-    int any_bounce = 0, any_lut = 0;
-    for (auto& mb : g.m) {
-        any_bounce |= mb.p.bounce == LB_LATTICE_NODE;
-        any_lut |= mb.p.tau_lut > 1;
-    }
-    const TuneKey key(std::string(prop.gcnArchName), g.m[0].p.nx, max_ny, g.m[0].p.storage,
-                      g.m[0].p.collision, g.m[0].p.inplace, g.batched ? total : -1,
-                      g.m[0].p.tau_phi == 1.0, any_bounce, any_lut);
+    int max_ny = 0;
+    for (auto& mb : g.m) max_ny = std::max(max_ny, mb.p.ny);
+    const TuneKey key = tune_key(g, prop.gcnArchName);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);

@@ -60,6 +60,24 @@ def _timed(torch, fn):
     return time.perf_counter() - t0
 
 
+def throughput(p, inp, storage="f64", steps=2000):
+    """MLUPS of one lattice of this set-up at the library's default tiling and
+    after lb_autotune (tiles reported), each timed over `steps` steps after a
+    warmup of the same length."""
+    torch = _torch()
+    out = {}
+    lat = _lattice(p, inp, storage)
+    for label in ("default", "tuned"):
+        if label == "tuned":
+            lbm.lb_autotune(lat, 50)
+        lbm.lb_step(lat, steps)
+        dt = _timed(torch, lambda: lbm.lb_step(lat, steps))
+        out[label] = {"tiles": list(lbm.lb_get_tuning(lat)),
+                      "mlups": round(p["nx"] * p["ny"] * steps / dt / 1e6, 1)}
+    lat.close()
+    return out
+
+
 def spurious_near_contact(phi, ux, uy, solid, radius=5.0):
     """Max |u| within `radius` of the phi = 0 crossings on the first fluid row
     above the bottom wall, and the global max |u| over fluid nodes."""
@@ -99,6 +117,7 @@ def c1(steps=2000, extra=(5000, 10000)):
         later.append((n, lbm.lb_contact_angle(lat, 0.0, 100.0, 3.5, 47.0, 0.5, 1)["theta"]))
     res["theta_later"] = later
     lat.close()
+    res["throughput"] = throughput(p, inp)
     return res
 
 
@@ -152,6 +171,8 @@ def c2(steps=20000, every=2000):
             out["runs"].append(run)
         out[f"{coll}_mlups_batched"] = 7 * 256 * 128 * steps / t_run / 1e6
         b.close()
+        p, inp = wl.c2_drop(coll, _dphi(90.0), seed=201)
+        out[f"{coll}_single_lattice"] = throughput(p, inp)
     return out
 
 
@@ -212,7 +233,9 @@ def c3(steps=100000, every=500, storage="f32", nx=1024, ny=64, ratios=(1, 10)):
             fit = {"slope": float(slope), "theta_a_mean": th_a,
                    "predicted_slope_gamma_cont": pred, "ratio": float(slope / pred)}
             good = sel & (ca > 0)
-            if good.sum() >= 3:
+            # extrapolate to Ca -> 0 only over a range of Ca wide enough to fix
+            # a slope (a meniscus moving at nearly constant Ca does not)
+            if good.sum() >= 3 and ca[good].max() >= 2.0 * ca[good].min():
                 k, c0 = np.polyfit(ca[good], np.cos(np.radians(thetas[good])), 1)
                 fit["cos_theta_a_vs_Ca"] = {"slope": float(k), "intercept": float(c0),
                                            "theta_a_at_Ca0": float(np.degrees(np.arccos(
@@ -220,6 +243,7 @@ def c3(steps=100000, every=500, storage="f32", nx=1024, ny=64, ratios=(1, 10)):
         res["runs"].append({"ratio": ratio, "tau_alpha": p["tau_alpha"],
                             "tau_beta": p["tau_beta"], "channel_width": h, "lc": lc,
                             "mlups": nx * ny * done / t_run / 1e6,
+                            "throughput": throughput(p, inp, storage),
                             "records": [list(r) for r in rec], "fit": fit})
     return res
 
