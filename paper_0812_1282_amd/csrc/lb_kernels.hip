@@ -734,7 +734,10 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
 
     // 16-bit formats: the loads of ring row y + 3d and of f_0, f_1, f_3 of row
     // y + d are issued while row y is collided and consumed in the next step,
-    // so each row's memory latency overlaps a row of arithmetic.
+    // so each row's memory latency overlaps a row of arithmetic. The words are
+    // loaded whether or not the node is solid (every address is inside its
+    // row): a load that waited for the node's mask would wait for every load
+    // in flight, the previous row's stores included.
     constexpr bool kPF = F::packed;
     uint32_t rawM[kPF ? 9 : 1], rawH[kPF ? 9 : 1];  // words of this column, of the halo column
     uint32_t rawNbM = 0xFFu, rawNbH = 0xFFu;
@@ -745,10 +748,10 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
             const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
             rawNbM = used ? nrow[x] : 0xFFu;
-            if (rawNbM != 0xFFu) pairs_issue<S>(R, v, co, rawM);
+            if (used) pairs_issue<S>(R, v, co, rawM);
             if (halo) {
                 rawNbH = nrow[hx];
-                if (rawNbH != 0xFFu) pairs_issue<S>(R, v, hco, rawH);
+                pairs_issue<S>(R, v, hco, rawH);
             }
         }
     };
@@ -850,20 +853,23 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
                     const uint32_t bits = axis ? axis : (rec >> 4);
                     real sum = 0;
                     int cnt = 0;
-#pragma unroll
-                    for (int mm = 0; mm < 4; ++mm) {
+                    static_for<4>([&](auto mc) {
+                        // fluid neighbour s + e_m, m = mm + 1 (axis) or mm + 5 (diagonal)
+                        constexpr int mm = decltype(mc)::value;
+                        constexpr int exa = EX[mm + 1], eya = EY[mm + 1];
+                        constexpr int exd = EX[mm + 5], eyd = EY[mm + 5];
                         if ((bits >> mm) & 1u) {
-                            // fluid neighbour s + e_m, m = mm + 1 (axis) or mm + 5 (diagonal)
-                            const int ex = axis ? EX[mm + 1] : EX[mm + 5];
-                            const int ey = axis ? EY[mm + 1] : EY[mm + 5];
+                            const int ex = axis ? exa : exd;
+                            const int ey = axis ? eya : eyd;
                             sum += sphi[(y + EY[k] + ey) & (kNR - 1)][c + EX[k] + ex];
                             ++cnt;
                         }
-                    }
-                    real gv = 0;
-                    if (cnt > 0)
-                        gv = sum / (real)cnt - (axis ? dw : (real)1.4142135623730951 * dw);
-                    pn[k] = gv;
+                    });
+                    // Formed without a branch on cnt, so that the loads of rec and
+                    // dw are consumed on every path through this node's code.
+                    const real scale = axis ? (real)1 : (real)1.4142135623730951;
+                    const real gv = sum / (real)(cnt > 0 ? cnt : 1) - scale * dw;
+                    pn[k] = cnt > 0 ? gv : (real)0;
                 }
             }
         }
@@ -1158,19 +1164,35 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
         load_state_row(ys - d);
         __syncthreads();
     }
-    {
+    if constexpr (kPF) {
+        // the first four ring rows through the same issue / decode pair, each
+        // row's loads issued before the previous row is decoded
         real gt[9], ft[9], st, bt;
         uint32_t nbt;
-        fill_row(ys - 2 * d, gt, ft, nbt, st, bt);
+        raw_issue(ys - 2 * d);
+        raw_finish(ys - 2 * d, gt, ft, nbt, st, bt);
+        raw_issue(ys - d);
+        raw_finish(ys - d, gt, ft, nbt, st, bt);
+        raw_issue(ys);
+        raw_finish(ys, gA, fA, nbA, sA, bA);
+        raw_issue(ys + d);
+        f_issue(ys, nbA);
+        raw_finish(ys + d, gB, fB, nbB, sB, bB);
+    } else {
+        {
+            real gt[9], ft[9], st, bt;
+            uint32_t nbt;
+            fill_row(ys - 2 * d, gt, ft, nbt, st, bt);
+            if constexpr (F::gstate) __syncthreads();
+            fill_row(ys - d, gt, ft, nbt, st, bt);
+            if constexpr (F::gstate) __syncthreads();
+        }
+        fill_row(ys, gA, fA, nbA, sA, bA);
         if constexpr (F::gstate) __syncthreads();
-        fill_row(ys - d, gt, ft, nbt, st, bt);
+        fill_row(ys + d, gB, fB, nbB, sB, bB);
         if constexpr (F::gstate) __syncthreads();
+        f_issue(ys, nbA);
     }
-    fill_row(ys, gA, fA, nbA, sA, bA);
-    if constexpr (F::gstate) __syncthreads();
-    fill_row(ys + d, gB, fB, nbB, sB, bB);
-    if constexpr (F::gstate) __syncthreads();
-    f_issue(ys, nbA);
     raw_issue(ys + 2 * d);
     // Unrolled by three so the three rows of pulled values rotate roles
     // without copies (the last argument: the mask of the next row).
