@@ -298,6 +298,13 @@ __device__ inline void stp(Rsrc r, const View& v, const ColOff& co, typename Fmt
 }
 
 __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// Row index v modulo n for any v: the sweep's look-ahead rows can lie more than
+// one lattice height beyond a short lattice's rows (n >= 3, reach up to 3 rows
+// past a strip of one row).
+__device__ inline int wrap_row(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
 
 template <int N, class F>
 __device__ inline void static_for(F&& f) {
@@ -628,22 +635,42 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     const bool shalo = t < 6;
     const int scol = t < 3 ? t : BX + t;
     const uint32_t sx = (uint32_t)(((x0 - 3 + scol) % nx + nx) % nx);
-    auto load_state_row = [&](int yy) __attribute__((always_inline)) {
+    // The state columns the used lanes read.
+    const bool sused = x0 + t <= nx + 2;
+    // state_issue loads row yy into registers (stM, and stH for the halo
+    // lanes); state_commit writes the registers of the row loaded last into
+    // the ring. The sweep commits a row one step after issuing it, so its
+    // loads are in flight during a row of arithmetic.
+    SW stM[F::gstate ? 4 : 1], stH[F::gstate ? 4 : 1];
+    auto state_issue = [&](int yy) __attribute__((always_inline)) {
         if constexpr (F::gstate) {
-            const Rsrc rr = row_rsrc(src, v, wrap(yy, ny));
-            auto ld = [&](uint32_t xx, int col) {
+            const Rsrc rr = row_rsrc(src, v, wrap_row(yy, ny));
+            auto ld = [&](uint32_t xx, SW* o) {
                 if constexpr (S == ST_F32C)
-                    sst[yy & 3][0][col] = __builtin_bit_cast(
+                    o[0] = __builtin_bit_cast(
                         float, buf_ld<uint32_t>(rr, xx * 4, F::template poff<9>(v)));
                 else
-                    sst[yy & 3][0][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<9>(v));
-                sst[yy & 3][1][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<10>(v));
-                sst[yy & 3][2][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<11>(v));
-                sst[yy & 3][3][col] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<12>(v));
+                    o[0] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<9>(v));
+                o[1] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<10>(v));
+                o[2] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<11>(v));
+                o[3] = buf_ld<SW>(rr, xx * sizeof(SW), F::template poff<12>(v));
             };
-            if (x0 + t <= nx + 2) ld(x, t + 3);  // the state columns the used lanes read
-            if (shalo) ld(sx, scol);
+            if (sused) ld(x, stM);
+            if (shalo) ld(sx, stH);
         }
+    };
+    auto state_commit = [&](int yy) __attribute__((always_inline)) {
+        if constexpr (F::gstate) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (sused) sst[yy & 3][k][t + 3] = stM[k];
+                if (shalo) sst[yy & 3][k][scol] = stH[k];
+            }
+        }
+    };
+    auto load_state_row = [&](int yy) __attribute__((always_inline)) {
+        state_issue(yy);
+        state_commit(yy);
     };
     // g-state at ring slot sl, column col: phi = b + q and the g^eq inputs.
     auto gstate_at = [&](int sl, int col, real& ph, real& gm, real& gu, real& gv, real& q,
@@ -695,19 +722,23 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     auto fill_row = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
                         real& base) __attribute__((always_inline)) {
         if constexpr (F::gstate) {
-            // the g-state two rows further on, then phi of row yy from the
-            // state rows yy - 1, yy, yy + 1 loaded before
-            load_state_row(yy + 2 * d);
-            const GLOBAL uint8_t* nrow = nbr + (size_t)wrap(yy, ny) * v.pitch;
+            // the node masks first (their wait then leaves the state loads in
+            // flight), the g-state two rows further on into the ring, the
+            // loads of the row after it, then phi of row yy from the state
+            // rows yy - 1, yy, yy + 1 committed before
+            const GLOBAL uint8_t* nrow = nbr + (size_t)wrap_row(yy, ny) * v.pitch;
             nb = nrow[x];
+            const uint32_t hnb = halo ? nrow[hx] : 0xFFu;
+            state_commit(yy + 2 * d);
+            state_issue(yy + 3 * d);
             sphi[yy & (kNR - 1)][t + 2] = phi_gstate(yy, t + 3, nb, small, base);
             if (halo) {
                 real hs, hb;
-                sphi[yy & (kNR - 1)][hcol] = phi_gstate(yy, hcol + 1, nrow[hx], hs, hb);
+                sphi[yy & (kNR - 1)][hcol] = phi_gstate(yy, hcol + 1, hnb, hs, hb);
             }
             return;
         }
-        const int y = wrap(yy, ny);
+        const int y = wrap_row(yy, ny);
         const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
         nb = nrow[x];
         if constexpr (M != 0) {
@@ -744,7 +775,7 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     real pf0 = 0, pf1 = 0, pf3 = 0;
     auto raw_issue = [&](int yy) __attribute__((always_inline)) {
         if constexpr (kPF) {
-            const int y = wrap(yy, ny);
+            const int y = wrap_row(yy, ny);
             const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
             rawNbM = used ? nrow[x] : 0xFFu;
@@ -759,7 +790,7 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     auto raw_finish = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
                           real& base) __attribute__((always_inline)) {
         if constexpr (kPF) {
-            const int y = wrap(yy, ny);
+            const int y = wrap_row(yy, ny);
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
             nb = rawNbM;
             small = 0;
@@ -788,7 +819,7 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     auto f_issue = [&](int yy, uint32_t nbr_) __attribute__((always_inline)) {
         if constexpr (kPF) {
             if (active && nbr_ != 0xFFu) {
-                const int y = wrap(yy, ny);
+                const int y = wrap_row(yy, ny);
                 const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
                 pf0 = ldp<S, 0>(R.r[0], v, co, 0);
                 pf1 = (nbr_ & 1u) ? ldp<S, 2>(R.r[0], v, co, 0) : ldp<S, 1>(R.r[0], v, co, 1);
@@ -1162,6 +1193,7 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
         load_state_row(ys - 3 * d);
         load_state_row(ys - 2 * d);
         load_state_row(ys - d);
+        state_issue(ys);
         __syncthreads();
     }
     if constexpr (kPF) {
