@@ -22,7 +22,8 @@ duration measured with HIP events on the stream the kernels run on;
 16-bit formats, whose f_0, f_1, f_3 are 32-bit). `traffic` is the HBM rate from the committed rocprofv3 counter summary
 (profiles/sweep_traffic_4096x2048.json: FETCH_SIZE + WRITE_SIZE per launch,
 calibrated on a copy of known size) over the same launch duration, reported
-only while the kernel sources hash as they did when the counters were taken.
+only while the kernel sources hash as they did when the counters were taken;
+`traffic_over_stored` is that traffic over the stored bytes per launch.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on the host cores.
 """
@@ -265,8 +266,8 @@ def main():
                      "frac_stored": round(r["frac_stored"], 4),
                      "stored_bytes_per_lu": STORED_BYTES_PER_LU[head],
                      "traffic": traffic_gbs(head),
-                     "traffic_ratio": (round(traffic[head]["ratio"], 4)
-                                       if traffic and head in traffic else None),
+                     "traffic_over_stored": (round(traffic[head]["ratio"], 4)
+                                             if traffic and head in traffic else None),
                      "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1)},
         "variants": {s: {"mlups": round(v["mlups"], 1), "mlups_fluid": round(v["mlups_fluid"], 1),
                          "ms_per_step": round(v["ms_per_step"], 5),
