@@ -14,6 +14,14 @@ this module. Nothing here is shared with the HIP library.
                                angle with the wall
   flat_profile                 the discrete flat interface: Eq. (chempot) with
                                the Laplacian of Eq. (best) and uniform mu
+  wall_film_profile            the discrete equilibrium of a film between two
+                               wetting walls (Sec. II, ghost rows of reading R4)
+                               at a given total phi, by Newton
+  wall_tension,                the discrete wall and interface tensions of the
+  discrete_interface_tension   free energy of Eqs. (freeen), (bulkfe) on the
+                               lattice (bulk term per node, kappa/2 (d phi)^2 per
+                               link, the wall term at the first fluid row)
+  discrete_young_angle         Eq. (Young) with those discrete tensions
 """
 import math
 

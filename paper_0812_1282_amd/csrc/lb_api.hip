@@ -1095,7 +1095,8 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     // schedule, with the strip heights scaled per member (member_rows).
     std::vector<std::tuple<int, int, int>> cands;
     for (int bx : {64, 128, 256, 512, 1024})
-        for (int rows : {8, 16, 32, 64, 128}) cands.emplace_back(LB_SCHEDULE_STEPWISE, bx, rows);
+        for (int rows : {4, 8, 16, 32, 64, 128})
+            cands.emplace_back(LB_SCHEDULE_STEPWISE, bx, rows);
     if (g.batched)
         for (int bx : {128, 256, 512})
             for (int rows : {4, 8, 16, 32}) cands.emplace_back(LB_SCHEDULE_PERSISTENT, bx, rows);
@@ -1123,13 +1124,27 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
             if (set_schedule(g, LB_SCHEDULE_STEPWISE) || set_tuning(g, bx, rows) ||
                 set_schedule(g, sched))
                 continue;
-            HIPCHK(enqueue_window(g, 2, g.parity, false, g.stream));
+            // Timed as the steps run: replays of one captured graph of `len`
+            // steps (an even count, so each replay starts at the same parity),
+            // after one untimed replay; the capture is not timed.
+            int len = 2;
+            while (len * 2 <= std::min(steps, kGraphSteps)) len *= 2;
+            const int reps = (steps + len - 1) / len;
+            hipGraphExec_t ge = nullptr;
+            int crc = capture_graph(g, len, g.parity, false, &ge);
+            if (crc) return crc;
+            struct ExecGuard {
+                hipGraphExec_t e;
+                ~ExecGuard() { (void)hipGraphExecDestroy(e); }
+            } guard{ge};
+            HIPCHK(hipGraphLaunch(ge, g.stream));
             HIPCHK(hipEventRecord(e0, g.stream));
-            HIPCHK(enqueue_window(g, steps, g.parity, false, g.stream));
+            for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(ge, g.stream));
             HIPCHK(hipEventRecord(e1, g.stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            ms /= (float)(reps * len);  // per step
             if (ms < best) {
                 best = ms;
                 best_bx = bx;
