@@ -293,8 +293,9 @@ int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs)
  * lb_batch_init picks the tile shape with lb_batch_autotune (4 timed steps per
  * candidate); lb_batch_autotune times the candidate shapes over the whole
  * ensemble with the state restored afterwards and keeps the fastest. The tile
- * order is fixed: each member's tiles row-major, members in order, dealt to
- * the XCDs in contiguous ranges. The choice never changes results.
+ * order is fixed by the tiling: whole members are dealt to the 8 XCDs, largest
+ * first, each to the XCD with the least work so far, and each XCD takes its
+ * tiles largest first. The choice never changes results.
  */
 int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
                   const double* const* wall_dphi, const double* const* phi0,

@@ -172,7 +172,9 @@ struct Group {
     double* d_diag = nullptr;
     int32_t* d_flag = nullptr;
     View* d_views = nullptr;
-    int n_tiles = 0;
+    int n_tiles = 0;             // logical tiles the allocation holds (largest tiling)
+    int n_step_slots = 0;        // workgroups of a stepwise batch launch (table entries)
+    int step_slots_max = 0;      // entries the stepwise table holds
     char* batch_alloc = nullptr;
     // Captured graphs, one per (window length 2^l, parity of its first step,
     // whether its first step carries the periodic check): index (l*2 + parity)*2 + check.
@@ -506,13 +508,39 @@ int build_tiles(Group& g) {
             }
     }
     first.push_back((int32_t)logical.size());
-    // Workgroup b takes logical tile xcd_tile(b, n): members' neighbouring
-    // tiles stay on one XCD.
+    // Stepwise table: workgroup b runs on XCD b % 8. Whole members are dealt
+    // to the 8 XCDs, largest first, each to the XCD with the least work so far
+    // (a tile's work: its rows times the tile width, idle lanes included), so
+    // a member's neighbouring tiles share one L2 and the XCDs get equal work;
+    // each XCD then takes its tiles largest first. XCD k's i-th tile is entry
+    // 8 i + k; shorter lists are padded with empty entries (member -1).
     const int n = (int)logical.size();
-    std::vector<Tile> tiles(n);
-    for (int b = 0; b < n; ++b) tiles[b] = logical[xcd_tile(b, n)];
-    if (tiles.size() > (size_t)g.n_tiles)
+    std::vector<int> morder(g.m.size());
+    std::vector<int64_t> mwork(g.m.size(), 0);
+    for (size_t k = 0; k < g.m.size(); ++k) morder[k] = (int)k;
+    for (const Tile& t : logical) mwork[t.member] += (int64_t)(t.y1 - t.y0) * g.block_x;
+    std::stable_sort(morder.begin(), morder.end(),
+                     [&](int a, int b) { return mwork[a] > mwork[b]; });
+    std::vector<std::vector<Tile>> bins(8);
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k : morder) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        for (int i = first[k]; i < first[k + 1]; ++i) bins[x].push_back(logical[i]);
+        load[x] += mwork[k];
+    }
+    size_t max_len = 0;
+    for (auto& bin : bins) {
+        std::stable_sort(bin.begin(), bin.end(), [](const Tile& a, const Tile& b) {
+            return a.y1 - a.y0 > b.y1 - b.y0;
+        });
+        max_len = std::max(max_len, bin.size());
+    }
+    std::vector<Tile> tiles(8 * max_len, Tile{-1, 0, 0, -1, 0, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t i = 0; i < bins[x].size(); ++i) tiles[8 * i + x] = bins[x][i];
+    if ((size_t)n > (size_t)g.n_tiles || tiles.size() > (size_t)g.step_slots_max)
         return fail(LB_EINVAL, "tile table too small for this tuning");
+    g.n_step_slots = (int)tiles.size();
     HIPCHK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice, g.stream));
     HIPCHK(hipMemcpyAsync(g.d_ptiles, logical.data(), logical.size() * sizeof(Tile),
@@ -610,7 +638,7 @@ hipError_t enqueue_one(Group& g, bool diag, int parity, hipStream_t st) {
                                reinterpret_cast<double*>(m0.base + L.off_diag),
                                reinterpret_cast<int32_t*>(m0.base + L.off_flag), st);
     }
-    const int nt = current_tiles(g);
+    const int nt = g.n_step_slots;
     hipError_t e = launch_sweep(m0.p.storage, m0.p.collision, g.block_x, diag,
                                 m0.p.tau_phi == 1.0, false, g.d_views, g.d_tiles, nt, 0, 0, g.rows,
                                 parity, g.d_partials, st);
@@ -1558,8 +1586,11 @@ int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* soli
         tiles_max += g.m[k].L.n_tiles_max;
     }
     g.n_tiles = (int)tiles_max;
+    // The stepwise table pads the XCDs' lists to one length: at most 8 entries
+    // per logical tile.
+    g.step_slots_max = (int)(8 * tiles_max);
     const size_t off_tiles = total;
-    const size_t off_first = off_tiles + round_up(tiles_max * sizeof(Tile), 256);
+    const size_t off_first = off_tiles + round_up(8 * tiles_max * sizeof(Tile), 256);
     const size_t off_part = off_first + round_up((size_t)(n + 1) * 4, 256);
     const size_t off_diag = off_part + round_up(tiles_max * kPartials * 8, 256);
     const size_t off_flag = off_diag + round_up((size_t)n * kPartials * 8, 256);

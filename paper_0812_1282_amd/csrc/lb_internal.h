@@ -76,7 +76,7 @@ struct View {
 };
 
 struct Tile {
-    int32_t member, tx, ty;
+    int32_t member, tx, ty;  // member -1: an empty entry (padding of a batch's stepwise table)
     int32_t id;      // logical tile index (member-major, row-major): its partial-sum record
     int32_t y0, y1;  // rows y0 .. y1-1 of the member (strip heights may differ per member)
 };

@@ -1289,6 +1289,7 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
                   int grid_x, int parity, double* __restrict__ partials) {
     if (tiles) {
         const Tile tl = tiles[blockIdx.x];
+        if (tl.member < 0) return;  // padding of a batch table (whole workgroup)
         sweep_tile<S, COLL, BX, DIAG, G1, M>(views, tl.member, tl.tx, tl.ty, tl.y0, tl.y1, tl.id,
                                              parity, partials);
     } else {
@@ -1469,6 +1470,7 @@ __global__ __launch_bounds__(1024) void wall_kernel(const View* __restrict__ vie
     int member = 0, tx, y0, y1;
     if (tiles) {
         const Tile tl = tiles[blockIdx.x];
+        if (tl.member < 0) return;  // padding of a batch table
         member = tl.member;
         tx = tl.tx;
         y0 = tl.y0;
