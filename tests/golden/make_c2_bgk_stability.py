@@ -23,7 +23,7 @@ from paper_0812_1282_amd import workloads as wl  # noqa: E402
 from tests.helpers import make_oracle  # noqa: E402
 
 STEPS, EVERY = 20000, 500
-TAU_BETA = (0.55, 0.6, 0.65, 0.7, 0.8, 1.0)
+TAU_BETA = (0.55, 0.56, 0.57, 0.58, 0.6, 0.65, 0.7, 0.8, 1.0)
 
 
 def near_contact_speed(phi, ux, uy, solid, radius=5.0):
