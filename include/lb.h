@@ -251,12 +251,14 @@ int lb_load(lb_handle* h, const char* path);
 
 /* Tile shape: set (lb_set_tuning), read (lb_get_tuning), or pick by timing
  * candidate shapes on the handle's own stream with the state restored
- * afterwards (lb_autotune: 64..1024 columns x 4..128 rows; each candidate
+ * afterwards (lb_autotune: 64..1024 columns x 1..128 rows; each candidate
  * timed over about steps_per_trial steps as replays of one captured graph,
  * the way lb_step runs them). The choice never changes results. A new lattice
  * starts with the shape lb_autotune chose for the same problem earlier in the
  * process on this kind of device, else with the tallest strips and widest
- * tiles (256 x 32 down to 64 x 4) that give at least one workgroup per CU. */
+ * tiles (256 x 32 down to 64 x 4) that give at least one workgroup per CU;
+ * a lattice whose step moves under 64 MB takes one-row strips (its step time
+ * is the latency of a strip's row walk, not bandwidth). */
 int lb_set_tuning(lb_handle* h, const lb_tuning* t);
 int lb_get_tuning(lb_handle* h, lb_tuning* t);
 int lb_autotune(lb_handle* h, int32_t steps_per_trial, lb_tuning* chosen);

