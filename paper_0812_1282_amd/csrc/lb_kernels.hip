@@ -432,6 +432,63 @@ __device__ inline void pairs_decode(const Rows& R, const View& v, const ColOff& 
     }
 }
 
+// Plain formats (FP64, FP32) with tau_phi = 1, two buffers: g_issue loads the
+// words of the nine g pulled at (x, y) and g_finish forms phi from them with
+// the arithmetic of phi9 (read mode 0). The sweep issues the loads of a ring
+// row's column and of its halo column before it waits for either, and without
+// waiting for the node's mask first.
+template <int S>
+struct GWords {
+    typename Fmt<S>::template E<9> w0;
+    typename Fmt<S>::template E<10> w[9];
+};
+template <int S>
+__device__ inline void g_issue(const Rows& R, const View& v, const ColOff& co, GWords<S>& o) {
+    using F = Fmt<S>;
+    o.w0 = buf_ld<typename F::template E<9>>(R.r[0], co.c9, F::template poff<9>(v));
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (i > 0) {
+            using E = typename F::template E<9 + i>;
+            o.w[i] = buf_ld<E>(R.r[src_row<0, i>()], co.c[src_col<0, i>()],
+                               F::template poff<9 + i>(v));
+        }
+    });
+}
+template <int S>
+__device__ inline typename Fmt<S>::real g_finish(const Rows& R, const View& v, const ColOff& co,
+                                                 uint32_t nb, const GWords<S>& o,
+                                                 typename Fmt<S>::real& small,
+                                                 typename Fmt<S>::real& base) {
+    using F = Fmt<S>;
+    using real = typename F::real;
+    real gv[9];
+    if constexpr (F::shifted) {
+        gv[0] = G0Code::q(o.w0);
+        base = G0Code::b(o.w0);
+    } else {
+        gv[0] = (real)o.w0;
+        base = 0;
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i) gv[i] = (real)o.w[i];
+    if (nb != 0u) {
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (i > 0) {
+                using E = typename F::template E<9 + OPP[i]>;
+                if ((nb >> (i - 1)) & 1u)
+                    gv[i] = (real)buf_ld<E>(R.r[0], co.c[0], F::template poff<9 + OPP[i]>(v));
+            }
+        });
+    }
+    real sg = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) sg += gv[i];
+    small = gv[0] + sg;
+    return F::shifted ? base + small : small;
+}
+
 template <int S>
 __device__ inline void pull_pairs(const Rows& R, const View& v, const ColOff& co, uint32_t nb,
                                   float fo[9], float go[9], float& base) {
@@ -755,6 +812,26 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
             return;
         }
         const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        if constexpr (!F::packed && G1) {
+            // the masks and the g words of this column and of the halo column
+            // are all issued before anything waits for them
+            GWords<S> wM, wH;
+            nb = used ? nb : 0xFFu;
+            const uint32_t hnb = halo ? nrow[hx] : 0xFFu;
+            if (used) g_issue<S>(R, v, co, wM);
+            if (halo) g_issue<S>(R, v, hco, wH);
+            small = 0;
+            base = 0;
+            real ph = 0;
+            if (nb != 0xFFu) ph = g_finish<S>(R, v, co, pull_mask(nb), wM, small, base);
+            sphi[yy & (kNR - 1)][t + 2] = ph;
+            if (halo) {
+                real hs = 0, hb = 0, hp = 0;
+                if (hnb != 0xFFu) hp = g_finish<S>(R, v, hco, pull_mask(hnb), wH, hs, hb);
+                sphi[yy & (kNR - 1)][hcol] = hp;
+            }
+            return;
+        }
         if (!used) nb = 0xFFu;
         sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
         if (halo) {
