@@ -55,7 +55,7 @@ ARITH = {"f64": "f64", "f32": "f32", "f16s": "f32", "bf16s": "f32", "f64c": "f64
          "f64ip": "f64", "f32ip": "f32"}
 GATE_DPHI, GATE_DTHETA = 1e-3, 0.5
 # Tile shapes (block_x, rows per workgroup) chosen by lb_autotune on this workload.
-DEFAULT_TILES = {"f64": (128, 128), "f32": (256, 64), "f16s": (1024, 32), "bf16s": (512, 32),
+DEFAULT_TILES = {"f64": (128, 128), "f32": (256, 64), "f16s": (512, 32), "bf16s": (512, 32),
                  "f64c": (256, 64), "f32c": (512, 32), "f64ip": (1024, 32), "f32ip": (1024, 32)}
 
 
