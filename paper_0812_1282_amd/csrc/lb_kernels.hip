@@ -775,6 +775,35 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
         base = b0;
         return base + small;
     };
+    // FP64 / FP32 with tau_phi = 1, two buffers: ring row yy in two halves.
+    // g_row_issue loads the masks and the g words of this column and of the
+    // halo column, all before anything waits for them; g_row_finish forms phi
+    // from them into the ring.
+    auto g_row_issue = [&](int yy, GWords<S>& wM, GWords<S>& wH, uint32_t& nbm,
+                           uint32_t& nbh) __attribute__((always_inline)) {
+        const int y = wrap_row(yy, ny);
+        const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        nbm = used ? nrow[x] : 0xFFu;
+        nbh = halo ? nrow[hx] : 0xFFu;
+        if (used) g_issue<S>(R, v, co, wM);
+        if (halo) g_issue<S>(R, v, hco, wH);
+    };
+    auto g_row_finish = [&](int yy, const GWords<S>& wM, const GWords<S>& wH, uint32_t nbm,
+                            uint32_t nbh, real& small, real& base) __attribute__((always_inline)) {
+        const int y = wrap_row(yy, ny);
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
+        small = 0;
+        base = 0;
+        real ph = 0;
+        if (nbm != 0xFFu) ph = g_finish<S>(R, v, co, pull_mask(nbm), wM, small, base);
+        sphi[yy & (kNR - 1)][t + 2] = ph;
+        if (halo) {
+            real hs = 0, hb = 0, hp = 0;
+            if (nbh != 0xFFu) hp = g_finish<S>(R, v, hco, pull_mask(nbh), wH, hs, hb);
+            sphi[yy & (kNR - 1)][hcol] = hp;
+        }
+    };
     // Fill ring row yy: this thread's column and the halo columns.
     auto fill_row = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
                         real& base) __attribute__((always_inline)) {
@@ -811,27 +840,14 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
             if (halo) sphi[yy & (kNR - 1)][hcol] = brow[hx];
             return;
         }
-        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         if constexpr (!F::packed && G1) {
-            // the masks and the g words of this column and of the halo column
-            // are all issued before anything waits for them
             GWords<S> wM, wH;
-            nb = used ? nb : 0xFFu;
-            const uint32_t hnb = halo ? nrow[hx] : 0xFFu;
-            if (used) g_issue<S>(R, v, co, wM);
-            if (halo) g_issue<S>(R, v, hco, wH);
-            small = 0;
-            base = 0;
-            real ph = 0;
-            if (nb != 0xFFu) ph = g_finish<S>(R, v, co, pull_mask(nb), wM, small, base);
-            sphi[yy & (kNR - 1)][t + 2] = ph;
-            if (halo) {
-                real hs = 0, hb = 0, hp = 0;
-                if (hnb != 0xFFu) hp = g_finish<S>(R, v, hco, pull_mask(hnb), wH, hs, hb);
-                sphi[yy & (kNR - 1)][hcol] = hp;
-            }
+            uint32_t hnb;
+            g_row_issue(yy, wM, wH, nb, hnb);
+            g_row_finish(yy, wM, wH, nb, hnb, small, base);
             return;
         }
+        const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
         if (!used) nb = 0xFFu;
         sphi[yy & (kNR - 1)][t + 2] = phi_of(R, nb, co, g, fp, small, base);
         if (halo) {
@@ -850,31 +866,36 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
     uint32_t rawM[kPF ? 9 : 1], rawH[kPF ? 9 : 1];  // words of this column, of the halo column
     uint32_t rawNbM = 0xFFu, rawNbH = 0xFFu;
     real pf0 = 0, pf1 = 0, pf3 = 0;
-    auto raw_issue = [&](int yy) __attribute__((always_inline)) {
+    // The words of ring row yy into (wm, wh, nbm, nbh): this column's, the
+    // halo column's, and their masks.
+    auto raw_issue_to = [&](int yy, uint32_t (&wm)[kPF ? 9 : 1], uint32_t (&wh)[kPF ? 9 : 1],
+                            uint32_t& nbm, uint32_t& nbh) __attribute__((always_inline)) {
         if constexpr (kPF) {
             const int y = wrap_row(yy, ny);
             const GLOBAL uint8_t* nrow = nbr + (size_t)y * v.pitch;
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
-            rawNbM = used ? nrow[x] : 0xFFu;
-            if (used) pairs_issue<S>(R, v, co, rawM);
+            nbm = used ? nrow[x] : 0xFFu;
+            if (used) pairs_issue<S>(R, v, co, wm);
             if (halo) {
-                rawNbH = nrow[hx];
-                pairs_issue<S>(R, v, hco, rawH);
+                nbh = nrow[hx];
+                pairs_issue<S>(R, v, hco, wh);
             }
         }
     };
-    // phi of ring row yy from the words raw_issue loaded (as fill_row forms it)
-    auto raw_finish = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
-                          real& base) __attribute__((always_inline)) {
+    // phi of ring row yy from words raw_issue_to loaded (as fill_row forms it)
+    auto raw_finish_from = [&](int yy, const uint32_t (&wm)[kPF ? 9 : 1],
+                               const uint32_t (&wh)[kPF ? 9 : 1], uint32_t nbm, uint32_t nbh,
+                               real g[9], real fp[9], uint32_t& nb, real& small,
+                               real& base) __attribute__((always_inline)) {
         if constexpr (kPF) {
             const int y = wrap_row(yy, ny);
             const Rows R = rows_of(src, v, y, wrap(y - 1, ny), wrap(y + 1, ny));
-            nb = rawNbM;
+            nb = nbm;
             small = 0;
             base = 0;
             real ph = 0;
             if (nb != 0xFFu) {
-                pairs_decode<S>(R, v, co, nb, rawM, fp, g, base);
+                pairs_decode<S>(R, v, co, nb, wm, fp, g, base);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) small += g[i];
                 ph = base + small;
@@ -882,8 +903,8 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
             sphi[yy & (kNR - 1)][t + 2] = ph;
             if (halo) {
                 real hg[9], hf[9], hs = 0, hb = 0, hp = 0;
-                if (rawNbH != 0xFFu) {
-                    pairs_decode<S>(R, v, hco, rawNbH, rawH, hf, hg, hb);
+                if (nbh != 0xFFu) {
+                    pairs_decode<S>(R, v, hco, nbh, wh, hf, hg, hb);
 #pragma unroll
                     for (int i = 0; i < 9; ++i) hs += hg[i];
                     hp = hb + hs;
@@ -891,6 +912,13 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
                 sphi[yy & (kNR - 1)][hcol] = hp;
             }
         }
+    };
+    auto raw_issue = [&](int yy) __attribute__((always_inline)) {
+        raw_issue_to(yy, rawM, rawH, rawNbM, rawNbH);
+    };
+    auto raw_finish = [&](int yy, real g[9], real fp[9], uint32_t& nb, real& small,
+                          real& base) __attribute__((always_inline)) {
+        raw_finish_from(yy, rawM, rawH, rawNbM, rawNbH, g, fp, nb, small, base);
     };
     // f_0, f_1, f_3 of row yy (pull sources as in the sweep; nbr_ its mask)
     auto f_issue = [&](int yy, uint32_t nbr_) __attribute__((always_inline)) {
@@ -1274,19 +1302,35 @@ __device__ __forceinline__ void sweep_tile(const View* __restrict__ views, int m
         __syncthreads();
     }
     if constexpr (kPF) {
-        // the first four ring rows through the same issue / decode pair, each
-        // row's loads issued before the previous row is decoded
+        // the first four ring rows two at a time: both rows' loads are in
+        // flight before either is decoded (the second set of words lives only
+        // here); f of the first collided row is issued with the fourth row
         real gt[9], ft[9], st, bt;
-        uint32_t nbt;
+        uint32_t nbt, w2m[9], w2h[9], n2m = 0xFFu, n2h = 0xFFu;
         raw_issue(ys - 2 * d);
+        raw_issue_to(ys - d, w2m, w2h, n2m, n2h);
         raw_finish(ys - 2 * d, gt, ft, nbt, st, bt);
-        raw_issue(ys - d);
-        raw_finish(ys - d, gt, ft, nbt, st, bt);
+        raw_finish_from(ys - d, w2m, w2h, n2m, n2h, gt, ft, nbt, st, bt);
         raw_issue(ys);
+        raw_issue_to(ys + d, w2m, w2h, n2m, n2h);
         raw_finish(ys, gA, fA, nbA, sA, bA);
-        raw_issue(ys + d);
         f_issue(ys, nbA);
-        raw_finish(ys + d, gB, fB, nbB, sB, bB);
+        raw_finish_from(ys + d, w2m, w2h, n2m, n2h, gB, fB, nbB, sB, bB);
+    } else if constexpr (!F::gstate && G1 && M == 0) {
+        // FP64 / FP32: the first four ring rows two at a time, as above
+        GWords<S> a1, a2, b1, b2;
+        uint32_t na1, na2, nb1, nb2;
+        real st, bt;
+        g_row_issue(ys - 2 * d, a1, a2, na1, na2);
+        g_row_issue(ys - d, b1, b2, nb1, nb2);
+        g_row_finish(ys - 2 * d, a1, a2, na1, na2, st, bt);
+        g_row_finish(ys - d, b1, b2, nb1, nb2, st, bt);
+        g_row_issue(ys, a1, a2, na1, na2);
+        g_row_issue(ys + d, b1, b2, nb1, nb2);
+        g_row_finish(ys, a1, a2, na1, na2, sA, bA);
+        nbA = na1;
+        g_row_finish(ys + d, b1, b2, nb1, nb2, sB, bB);
+        nbB = nb1;
     } else {
         {
             real gt[9], ft[9], st, bt;
