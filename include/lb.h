@@ -295,9 +295,11 @@ int lb_bandwidth_probe(size_t bytes, int32_t repeats, void* stream, double* gbs)
  * lb_batch_init picks the tile shape with lb_batch_autotune (4 timed steps per
  * candidate); lb_batch_autotune times the candidate shapes over the whole
  * ensemble with the state restored afterwards and keeps the fastest. The tile
- * order is fixed by the tiling: whole members are dealt to the 8 XCDs, largest
- * first, each to the XCD with the least work so far, and each XCD takes its
- * tiles largest first. The choice never changes results.
+ * order is fixed by the tiling: members are dealt to the 8 XCDs, largest
+ * first, each to the XCD with the least work so far (a member with more than
+ * an eighth of the work is first cut into contiguous runs of equal work, at
+ * most an eighth each, dealt the same way), and each XCD takes its tiles
+ * largest first. The choice never changes results.
  */
 int lb_batch_init(int32_t n, const lb_params* params, const uint8_t* const* solid,
                   const double* const* wall_dphi, const double* const* phi0,
@@ -316,9 +318,10 @@ int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen);
 /* Schedule of a batch's timesteps. LB_SCHEDULE_STEPWISE: one launch per step over
  * every member's tiles (the tile table above). LB_SCHEDULE_PERSISTENT: a window
  * of steps (up to 32, the graph windows of lb_step) is one launch of as many
- * workgroups as fit on the device, which take (step, tile) items in order from
- * a counter and sweep a tile as soon as the tiles around it (within one tile,
- * same member) have finished the previous step: no barrier between members or
+ * workgroups as fit on the device (at most two steps' tiles), which take
+ * (step, tile) items in order from a counter and sweep a tile as soon as the
+ * tiles around it (within one tile, same member) have finished the previous
+ * step: no barrier between members or
  * steps, so members of different sizes and the end of one step overlap the
  * start of the next. A step with the periodic check runs stepwise. Members
  * narrower than block_x get proportionally taller strips under either
@@ -327,8 +330,8 @@ int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen);
  * members (LB_EINVAL otherwise). Results are identical under both schedules.
  * spin_limit: polls a waiting workgroup makes before it gives up (0 = the
  * default, 2^20; a wait also gives up after about one second); when one gives
- * up, every workgroup leaves and the next synchronising call on the batch
- * returns LB_EHIP (the state is then invalid).
+ * up, every workgroup leaves and every later read of the batch (fields,
+ * populations, contact angle) returns LB_EHIP (the state is then invalid).
  * lb_batch_autotune (and lb_batch_init without a tuning) times both schedules
  * and keeps the faster. */
 #define LB_SCHEDULE_STEPWISE 0

@@ -508,12 +508,15 @@ int build_tiles(Group& g) {
             }
     }
     first.push_back((int32_t)logical.size());
-    // Stepwise table: workgroup b runs on XCD b % 8. Whole members are dealt
-    // to the 8 XCDs, largest first, each to the XCD with the least work so far
-    // (a tile's work: its rows times the tile width, idle lanes included), so
-    // a member's neighbouring tiles share one L2 and the XCDs get equal work;
-    // each XCD then takes its tiles largest first. XCD k's i-th tile is entry
-    // 8 i + k; shorter lists are padded with empty entries (member -1).
+    // Stepwise table: workgroup b runs on XCD b % 8. Members are dealt to the
+    // 8 XCDs, largest first, each to the XCD with the least work so far (a
+    // tile's work: its rows times the tile width, idle lanes included), so a
+    // member's neighbouring tiles share one L2 and the XCDs get equal work; a
+    // member with more work than an eighth of the total is first cut into
+    // contiguous runs of its tiles (row-major) of equal work, at most an eighth
+    // each, and the runs are dealt the same way. Each XCD then takes its tiles
+    // largest first. XCD k's i-th tile is entry 8 i + k; shorter lists are
+    // padded with empty entries (member -1).
     const int n = (int)logical.size();
     std::vector<int> morder(g.m.size());
     std::vector<int64_t> mwork(g.m.size(), 0);
@@ -521,12 +524,27 @@ int build_tiles(Group& g) {
     for (const Tile& t : logical) mwork[t.member] += (int64_t)(t.y1 - t.y0) * g.block_x;
     std::stable_sort(morder.begin(), morder.end(),
                      [&](int a, int b) { return mwork[a] > mwork[b]; });
+    int64_t work = 0;
+    for (int64_t w : mwork) work += w;
+    const int64_t share = (work + 7) / 8;
     std::vector<std::vector<Tile>> bins(8);
     int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k : morder) {
-        const int x = (int)(std::min_element(load, load + 8) - load);
-        for (int i = first[k]; i < first[k + 1]; ++i) bins[x].push_back(logical[i]);
-        load[x] += mwork[k];
+        const int64_t runs = share > 0 ? std::max<int64_t>(1, (mwork[k] + share - 1) / share) : 1;
+        int64_t acc = 0;
+        int run = -1, x = 0;
+        for (int i = first[k]; i < first[k + 1]; ++i) {
+            const int64_t w = (int64_t)(logical[i].y1 - logical[i].y0) * g.block_x;
+            // the run holding the middle of this tile's work
+            const int r = (int)std::min<int64_t>(runs - 1, (2 * acc + w) * runs / (2 * mwork[k]));
+            if (r != run) {
+                run = r;
+                x = (int)(std::min_element(load, load + 8) - load);
+            }
+            bins[x].push_back(logical[i]);
+            load[x] += w;
+            acc += w;
+        }
     }
     size_t max_len = 0;
     for (auto& bin : bins) {
@@ -607,7 +625,8 @@ hipError_t enqueue_persistent(Group& g, int len, int parity, hipStream_t st) {
     const int nt = current_tiles(g);
     hipError_t e = launch_fill(g.d_sync + 1, 0, (size_t)(nt + 1) * 4, st);
     if (e != hipSuccess) return e;
-    const int grid = (int)std::min<int64_t>(g.persist_grid, (int64_t)nt * len);
+    // No more workgroups than two steps' tiles: further ones could only wait.
+    const int grid = (int)std::min<int64_t>(g.persist_grid, (int64_t)nt * std::min(len, 2));
     return launch_persistent(m0.p.storage, m0.p.collision, g.block_x, m0.p.tau_phi == 1.0,
                              g.d_views, g.d_ptiles, g.d_deps, nt, len, parity, grid, g.d_sync + 2,
                              reinterpret_cast<uint32_t*>(g.d_sync + 1), g.d_sync, g.spin_limit,
@@ -737,7 +756,9 @@ int group_step(Group& g, int64_t nsteps) {
     return LB_OK;
 }
 
-int check_flag(Group& g) {
+// Whether every persistent window of a batch ran to completion: a window whose
+// wait gave up leaves the state invalid, which every read of a batch reports.
+int check_windows(Group& g) {
     if (g.batched && g.d_sync) {
         int32_t err = 0;
         HIPCHK(hipMemcpyAsync(&err, g.d_sync, 4, hipMemcpyDeviceToHost, g.stream));
@@ -746,6 +767,11 @@ int check_flag(Group& g) {
             return fail(LB_EHIP, "persistent schedule: a wait for a neighbouring tile exceeded "
                                  "its poll limit; the state is not valid");
     }
+    return LB_OK;
+}
+
+int check_flag(Group& g) {
+    if (int rc = check_windows(g)) return rc;
     for (size_t k = 0; k < g.m.size(); ++k) {
         int32_t flag = 0;
         const int32_t* src = g.batched ? g.d_flag + k
@@ -1676,15 +1702,19 @@ int lb_batch_read_fields(lb_batch* b, int32_t k, double* phi, double* rho, doubl
 int lb_batch_read_populations(lb_batch* b, int32_t k, double* f, double* g) {
     int rc = check_member(b, k);
     if (rc) return rc;
-    return read_populations(b->g, k, f, g);
+    rc = read_populations(b->g, k, f, g);
+    if (rc) return rc;
+    return check_windows(b->g);
 }
 
 int lb_batch_contact_angle(lb_batch* b, int32_t k, double x_lo, double x_hi, double y_lo,
                            double y_hi, double y_wall, int32_t wall_dir, double* theta_deg) {
     int rc = check_member(b, k);
     if (rc) return rc;
-    return contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
-                         nullptr, nullptr, nullptr);
+    rc = contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
+                       nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    return check_windows(b->g);
 }
 
 int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen) {

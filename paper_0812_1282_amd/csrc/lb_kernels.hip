@@ -1442,10 +1442,10 @@ void sweep_kernel(const View* __restrict__ views, const Tile* __restrict__ tiles
 // Memory ordering: a tile's populations are written by all its threads; each
 // wave waits for its stores to complete before the barrier, after which thread
 // 0 makes them visible device-wide (other XCDs included) with one agent-scope
-// release fence and publishes the step with an atomic store. A waiting
-// thread polls done[] with relaxed agent-scope loads and then issues one
-// agent-scope acquire fence; the barrier that follows orders the tile's pulls
-// after it.
+// release fence (an L2 write-back), waits for that write-back to complete,
+// and publishes the step with an atomic store. A waiting thread polls done[]
+// with relaxed agent-scope loads and then issues one agent-scope acquire
+// fence; the barrier that follows orders the tile's pulls after it.
 constexpr uint64_t kWaitTicks = 100000000;  // one second of the 100 MHz wall clock
 template <int S, int COLL, int BX, bool G1>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves<S>)))
@@ -1503,10 +1503,14 @@ void sweep_persistent_kernel(const View* __restrict__ views, const Tile* __restr
                                               (parity0 + k) & 1, nullptr);
         // Every wave waits until its stores have completed (reached L2), then
         // the barrier; thread 0's agent-scope release (one L2 write-back for the
-        // workgroup) then covers the whole tile when it publishes the step.
+        // workgroup) then covers the whole tile when it publishes the step. The
+        // explicit wait keeps the publication behind the completed write-back.
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (t == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (t == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+        }
         prev_j = j;
         prev_k = k;
     }

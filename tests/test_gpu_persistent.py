@@ -2,7 +2,8 @@
 work items (step, tile) taken in order, a tile swept once its neighbouring tiles
 have finished the previous step. Results must equal the stepwise schedule (one
 launch per step) and solo runs bit for bit; a wait that exceeds its poll limit
-must surface as an error, with every workgroup leaving."""
+must surface as an error on every read of the batch, with every workgroup
+leaving."""
 import sys
 
 import numpy as np
@@ -101,6 +102,9 @@ def test_persistent_wait_limit_reports_an_error():
     lbm.lb_batch_step(b, 32)
     with pytest.raises(lbm.LbError) as e:
         lbm.lb_batch_read_fields(b, 0)
+    assert e.value.code == lbm.LB_EHIP
+    with pytest.raises(lbm.LbError) as e:            # populations are not handed back
+        lbm.lb_batch_read_populations(b, 0)
     assert e.value.code == lbm.LB_EHIP
     b.close()
     ok = _batch(members, "f32", (256, 8), lbm.PERSISTENT)
