@@ -63,6 +63,28 @@ def test_batch_members_equal_solo_runs(storage):
     b.close()
 
 
+def test_members_cut_across_xcds_equal_solo_runs():
+    """A member with more than an eighth of the batch's work is cut into runs of
+    tiles dealt to several XCDs: a one-member batch, and a batch where one
+    member dominates, still equal their solo runs bit for bit."""
+    members = _members()
+    big, small = members[2], members[3]          # 128 x 64 and 67 x 13
+    for group in ([big], [big, small]):
+        say(f"case batch of {len(group)} with a cut member")
+        params = [lbm.make_params(p, "f32") for p, _ in group]
+        b = lbm.lb_batch_init(params, [inp for _, inp in group], tuning=(64, 4))
+        lbm.lb_batch_step(b, 40)
+        for k, (p, inp) in enumerate(group):
+            solo = lbm.lb_init(lbm.make_params(p, "f32"), inp["solid"], inp["phi0"],
+                               dphi=inp["dphi"], rho0=inp["rho0"])
+            lbm.lb_step(solo, 40)
+            fb, gb = lbm.lb_batch_read_populations(b, k)
+            fs, gs = lbm.lb_read_populations(solo)
+            assert np.array_equal(fb, fs) and np.array_equal(gb, gs), (len(group), k)
+            solo.close()
+        b.close()
+
+
 def test_batch_graph_path_and_contact_angle():
     members = _members()
     say("case batch graph path")
