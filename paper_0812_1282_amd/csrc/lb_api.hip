@@ -756,8 +756,9 @@ int group_step(Group& g, int64_t nsteps) {
     return LB_OK;
 }
 
-// Whether every persistent window of a batch ran to completion: a window whose
-// wait gave up leaves the state invalid, which every read of a batch reports.
+// Whether every persistent window of a batch enqueued so far ran to completion
+// (it waits for them): a window whose wait gave up leaves the state invalid,
+// which every read of a batch reports.
 int check_windows(Group& g) {
     if (g.batched && g.d_sync) {
         int32_t err = 0;
@@ -1702,19 +1703,19 @@ int lb_batch_read_fields(lb_batch* b, int32_t k, double* phi, double* rho, doubl
 int lb_batch_read_populations(lb_batch* b, int32_t k, double* f, double* g) {
     int rc = check_member(b, k);
     if (rc) return rc;
-    rc = read_populations(b->g, k, f, g);
+    rc = check_windows(b->g);
     if (rc) return rc;
-    return check_windows(b->g);
+    return read_populations(b->g, k, f, g);
 }
 
 int lb_batch_contact_angle(lb_batch* b, int32_t k, double x_lo, double x_hi, double y_lo,
                            double y_hi, double y_wall, int32_t wall_dir, double* theta_deg) {
     int rc = check_member(b, k);
     if (rc) return rc;
-    rc = contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
-                       nullptr, nullptr, nullptr);
+    rc = check_windows(b->g);
     if (rc) return rc;
-    return check_windows(b->g);
+    return contact_angle(b->g, k, x_lo, x_hi, y_lo, y_hi, y_wall, wall_dir, theta_deg, nullptr,
+                         nullptr, nullptr, nullptr);
 }
 
 int lb_batch_autotune(lb_batch* b, int32_t steps_per_trial, lb_tuning* chosen) {
