@@ -250,12 +250,13 @@ def test_mrt_at_unit_rates_is_bgk_tau_one():
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-@pytest.mark.parametrize("phase", [1.0, -1.0])
+@pytest.mark.parametrize("phase", [1.0, -1.0, 0.7, -0.7])
 def test_shear_wave_viscosity_on_gpu(storage, collision, phase):
-    """A shear wave u_x = U sin(k y) in one bulk phase decays at nu k^2 with
-    nu = (tau - 1/2)/3, tau = tau_alpha in the phi = +1 phase and tau_beta in
-    the phi = -1 phase (Eqs. (tau), (kine); MRT through its stress modes). A
-    check of the GPU path alone, in the headline format too."""
+    """A shear wave u_x = U sin(k y) in a uniform fluid at phi decays at nu k^2
+    with nu = (tau(phi) - 1/2)/3, tau(phi) = tau_beta + (phi + 1)/2 (tau_alpha -
+    tau_beta): the bulk phases phi = +1, -1 and mixtures at +-0.7, outside the
+    spinodal, which stay uniform (Eqs. (tau), (kine); MRT through its stress
+    modes). A check of the GPU path alone, in the headline format too."""
     nx, ny = 8, 48
     ta, tb = 1.3, 0.7
     p = wl.params(nx, ny, ta, tb, collision)
@@ -273,7 +274,7 @@ def test_shear_wave_viscosity_on_gpu(storage, collision, phase):
         ts.append((k + 1) * 50)
     lat.close()
     rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
-    nu = ((ta if phase > 0 else tb) - 0.5) / 3
+    nu = (tb + 0.5 * (phase + 1.0) * (ta - tb) - 0.5) / 3
     ratio = rate / (nu * (2 * np.pi / ny) ** 2)
     say(f"  decay rate / (nu k^2) = {ratio:.4f}")
     assert ratio == pytest.approx(1.0, abs=0.02)

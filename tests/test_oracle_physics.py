@@ -149,6 +149,35 @@ def test_shear_wave_viscosity(collision, tau):
     assert rate / (nu * (2 * np.pi / ny) ** 2) == pytest.approx(1.0, abs=0.02)
 
 
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("phi", [0.7, -0.7, 0.85])
+def test_shear_wave_viscosity_between_the_phases(collision, phi):
+    """tau between the bulk values, Eq. (tau): in a uniform mixture at phi (outside
+    the spinodal |phi| < 1/sqrt(3), so it stays uniform) a shear wave decays at
+    nu k^2 with nu = (tau(phi) - 1/2)/3 and tau(phi) = tau_beta + (phi + 1)/2
+    (tau_alpha - tau_beta), Eq. (kine). Interpolating 1/tau instead, or weighting
+    by phi rather than (phi + 1)/2, misses by 8% or more at these phi."""
+    nx, ny = 4, 48
+    ta, tb = 1.3, 0.7
+    p = wl.params(nx, ny, ta, tb, collision, zero_u_feq=0)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    inp = dict(solid=np.zeros((ny, nx), np.uint8), dphi=None, phi0=np.full((ny, nx), phi),
+               rho0=np.ones((ny, nx)), ux0=1e-3 * np.sin(2 * np.pi * y / ny),
+               uy0=np.zeros((ny, nx)))
+    o = make_oracle(p, inp)
+    ts, amps = [], []
+    for k in range(20):
+        o.step(50)
+        ph, _, ux, _ = o.fields()
+        amps.append((ux[:, 0] * np.sin(2 * np.pi * np.arange(ny) / ny)).sum() * 2 / ny)
+        ts.append((k + 1) * 50)
+    assert np.abs(ph - phi).max() < 1e-9           # the mixture stayed uniform
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    tau = tb + 0.5 * (phi + 1.0) * (ta - tb)
+    nu = (tau - 0.5) / 3
+    assert rate / (nu * (2 * np.pi / ny) ** 2) == pytest.approx(1.0, abs=0.02)
+
+
 def test_stripe_spurious_velocity_bgk():
     """Sec. V: a stripe between neutral walls, 28 x 15, tau = 10, has a steady
     spurious flow of order 1e-3 c under BGK; with periodic y instead of walls it has
