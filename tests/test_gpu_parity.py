@@ -281,6 +281,37 @@ def test_shear_wave_viscosity_on_gpu(storage, collision, phase):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f16s"])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("clamp, phase", [(1, 1.2), (1, -1.2), (0, 1.2)])
+def test_shear_wave_viscosity_with_tau_clamp_on_gpu(storage, collision, clamp, phase):
+    """tau_clamp on the GPU alone: a uniform fluid at phi = +-1.2 has its bulk
+    phase's viscosity with the clamp and the linear continuation of Eq. (tau)
+    without it, from the decay of a shear wave (Eq. (kine))."""
+    nx, ny = 8, 96
+    ta, tb = 3.0, 0.7
+    p = wl.params(nx, ny, ta, tb, collision, tau_clamp=clamp)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    inp = {"solid": np.zeros((ny, nx), np.uint8), "dphi": None,
+           "phi0": np.full((ny, nx), phase), "rho0": np.ones((ny, nx)),
+           "ux0": 1e-2 * np.sin(2 * np.pi * y / ny), "uy0": np.zeros((ny, nx))}
+    say(f"case shear wave tau_clamp={clamp} {storage} {collision} phi={phase}")
+    lat = gpu_lattice(p, inp, storage, zero_u_feq=0)
+    ts, amps = [], []
+    for k in range(20):
+        lbm.lb_step(lat, 50)
+        ux = lbm.lb_read_fields(lat)[2]
+        amps.append((ux[:, 0] * np.sin(2 * np.pi * np.arange(ny) / ny)).sum() * 2 / ny)
+        ts.append((k + 1) * 50)
+    lat.close()
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    c = max(-1.0, min(1.0, phase)) if clamp else phase
+    nu = (tb + 0.5 * (c + 1.0) * (ta - tb) - 0.5) / 3
+    ratio = rate / (nu * (2 * np.pi / ny) ** 2)
+    say(f"  decay rate / (nu k^2) = {ratio:.4f}")
+    assert ratio == pytest.approx(1.0, abs=0.02)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
 def test_laplace_pressure_on_gpu(storage):
     """Free drops of radius 8, 12, 16 in a periodic 64 x 64 box: p0 inside minus
     outside against 1/R has the slope of the discrete flat interface's tension

@@ -178,6 +178,35 @@ def test_shear_wave_viscosity_between_the_phases(collision, phi):
     assert rate / (nu * (2 * np.pi / ny) ** 2) == pytest.approx(1.0, abs=0.02)
 
 
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("clamp, phi", [(1, 1.2), (1, -1.2), (0, 1.2)])
+def test_shear_wave_viscosity_with_tau_clamp(collision, clamp, phi):
+    """The tau_clamp option: phi is clamped to [-1, 1] before Eq. (tau), so a
+    uniform fluid at phi = +-1.2 (stable, and it stays uniform) has the bulk
+    viscosity of its phase, while without the clamp the law continues linearly
+    (nu(1.2) is 9% above nu(1) at tau_alpha = 3, tau_beta = 0.7). Measured as the
+    decay rate nu k^2 of a shear wave, Eq. (kine)."""
+    nx, ny = 4, 96
+    ta, tb = 3.0, 0.7
+    p = wl.params(nx, ny, ta, tb, collision, zero_u_feq=0, tau_clamp=clamp)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    inp = dict(solid=np.zeros((ny, nx), np.uint8), dphi=None, phi0=np.full((ny, nx), phi),
+               rho0=np.ones((ny, nx)), ux0=1e-3 * np.sin(2 * np.pi * y / ny),
+               uy0=np.zeros((ny, nx)))
+    o = make_oracle(p, inp)
+    ts, amps = [], []
+    for k in range(20):
+        o.step(50)
+        ph, _, ux, _ = o.fields()
+        amps.append((ux[:, 0] * np.sin(2 * np.pi * np.arange(ny) / ny)).sum() * 2 / ny)
+        ts.append((k + 1) * 50)
+    assert np.abs(ph - phi).max() < 1e-9
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    c = max(-1.0, min(1.0, phi)) if clamp else phi
+    nu = (tb + 0.5 * (c + 1.0) * (ta - tb) - 0.5) / 3
+    assert rate / (nu * (2 * np.pi / ny) ** 2) == pytest.approx(1.0, abs=0.02)
+
+
 def test_stripe_spurious_velocity_bgk():
     """Sec. V: a stripe between neutral walls, 28 x 15, tau = 10, has a steady
     spurious flow of order 1e-3 c under BGK; with periodic y instead of walls it has
