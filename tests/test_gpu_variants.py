@@ -195,3 +195,34 @@ def test_tau_table_compressed_formats():
     say(f"  max|dphi| {d:.2e}")
     assert d <= 1e-3
     lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("bounce", [lbm.MIDLINK, LN])
+def test_channel_mode_decay_between_walls_on_gpu(storage, collision, bounce):
+    """On the GPU alone: the lowest shear mode between two no-slip walls of
+    either bounce-back kind decays at nu (pi/H)^2, H the number of fluid rows
+    (the wall plane halfway between the solid row and the first fluid row)."""
+    nx, ny, tau = 8, 34, 0.8
+    H = ny - 2
+    p = wl.params(nx, ny, tau, tau, collision, bounce=bounce)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    solid = wl.walls_mask(nx, ny)
+    prof = np.sin(np.pi * (y - 0.5) / H)
+    inp = {"solid": solid, "dphi": wl.wall_field(solid, 0.0), "phi0": np.ones((ny, nx)),
+           "rho0": np.ones((ny, nx)), "ux0": np.where(solid == 0, 1e-2 * prof, 0.0),
+           "uy0": np.zeros((ny, nx))}
+    say(f"case channel mode {storage} {collision} bounce={bounce}")
+    lat = gpu_lattice(p, inp, storage, zero_u_feq=0)
+    ts, amps = [], []
+    for k in range(20):
+        lbm.lb_step(lat, 100)
+        ux = lbm.lb_read_fields(lat)[2]
+        amps.append((ux[1:-1, 0] * prof[1:-1, 0]).sum() / (prof[1:-1, 0] ** 2).sum())
+        ts.append((k + 1) * 100)
+    lat.close()
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    ratio = rate / ((tau - 0.5) / 3 * (np.pi / H) ** 2)
+    say(f"  decay rate / (nu (pi/H)^2) = {ratio:.4f}")
+    assert ratio == pytest.approx(1.0, abs=0.01)

@@ -207,6 +207,37 @@ def test_shear_wave_viscosity_with_tau_clamp(collision, clamp, phi):
     assert rate / (nu * (2 * np.pi / ny) ** 2) == pytest.approx(1.0, abs=0.02)
 
 
+@pytest.mark.parametrize("bounce", [0, 1])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
+def test_channel_mode_decay_between_walls(bounce, collision, tau):
+    """No-slip walls of either bounce-back kind (mid-link, and the lattice-node
+    scheme of Fig. 9b): the lowest shear mode between two walls, u_x = U
+    sin(pi (y - y_w)/H), decays at nu (pi/H)^2 with the wall plane halfway
+    between the solid row and the first fluid row, so H is the number of fluid
+    rows (a wall on the solid nodes, H + 1, would be 6% off; a slipping or
+    absorbing wall far more)."""
+    nx, ny = 4, 34
+    H = ny - 2
+    p = wl.params(nx, ny, tau, tau, collision, zero_u_feq=0, bounce=bounce)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    solid = wl.walls_mask(nx, ny)
+    prof = np.sin(np.pi * (y - 0.5) / H)
+    inp = dict(solid=solid, dphi=wl.wall_field(solid, 0.0), phi0=np.ones((ny, nx)),
+               rho0=np.ones((ny, nx)), ux0=np.where(solid == 0, 1e-3 * prof, 0.0),
+               uy0=np.zeros((ny, nx)))
+    o = make_oracle(p, inp)
+    ts, amps = [], []
+    for k in range(20):
+        o.step(100)
+        ux = o.fields()[2]
+        amps.append((ux[1:-1, 0] * prof[1:-1, 0]).sum() / (prof[1:-1, 0] ** 2).sum())
+        ts.append((k + 1) * 100)
+    rate = -np.polyfit(ts[4:], np.log(amps[4:]), 1)[0]
+    nu = (tau - 0.5) / 3
+    assert rate / (nu * (np.pi / H) ** 2) == pytest.approx(1.0, abs=0.01)
+
+
 def test_stripe_spurious_velocity_bgk():
     """Sec. V: a stripe between neutral walls, 28 x 15, tau = 10, has a steady
     spurious flow of order 1e-3 c under BGK; with periodic y instead of walls it has
