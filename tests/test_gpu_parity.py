@@ -311,6 +311,30 @@ def test_shear_wave_viscosity_with_tau_clamp_on_gpu(storage, collision, clamp, p
     assert ratio == pytest.approx(1.0, abs=0.02)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_stratified_shear_decay_on_gpu(storage, collision):
+    """tau(phi) through interfaces on the GPU alone: a periodic stripe with a
+    shear flow along its flat interfaces decays as d_y(nu(y) d_y u) predicts,
+    nu(y) from the measured phi and Eq. (tau), viscosity ratio 15."""
+    from tests.test_oracle_physics import _slowest_excited_rate, stratified_shear_case
+    ny, ta, tb = 64, 2.0, 0.6
+    p, inp = stratified_shear_case(ny, ta, tb, collision)
+    say(f"case stratified shear {storage} {collision}")
+    lat = gpu_lattice(p, inp, storage, zero_u_feq=0)
+    ts, es = [], []
+    for k in range(60):
+        lbm.lb_step(lat, 100)
+        phi, rho, ux, uy = lbm.lb_read_fields(lat)
+        ts.append((k + 1) * 100)
+        es.append((rho[:, 0] * ux[:, 0] ** 2).sum())
+    lat.close()
+    lam = -np.polyfit(ts[30:], np.log(es[30:]), 1)[0] / 2
+    lam0 = _slowest_excited_rate(phi[:, 0], ta, tb, np.sin(2 * np.pi * np.arange(ny) / ny))
+    say(f"  rate / slowest excited rate of the continuum operator = {lam / lam0:.4f}")
+    assert lam / lam0 == pytest.approx(1.0, abs=0.015)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f16s"])
 def test_laplace_pressure_on_gpu(storage):
     """Free drops of radius 8, 12, 16 in a periodic 64 x 64 box: p0 inside minus

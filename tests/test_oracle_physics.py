@@ -238,6 +238,58 @@ def test_channel_mode_decay_between_walls(bounce, collision, tau):
     assert rate / (nu * (np.pi / H) ** 2) == pytest.approx(1.0, abs=0.01)
 
 
+def _slowest_excited_rate(phi_col, ta, tb, u0):
+    """Slowest decay rate of d/dy(nu(y) d/dy) on the periodic node grid, among
+    the eigenmodes the initial profile u0 excites; nu(y) = (tau(phi(y)) - 1/2)/3
+    with Eq. (tau), taken halfway between nodes as the mean of the two."""
+    ny = len(phi_col)
+    nu = (tb + 0.5 * (phi_col + 1.0) * (ta - tb) - 0.5) / 3
+    nh = 0.5 * (nu + np.roll(nu, -1))
+    L = np.zeros((ny, ny))
+    for j in range(ny):
+        L[j, (j + 1) % ny] += nh[j]
+        L[j, j] -= nh[j] + nh[j - 1]
+        L[j, (j - 1) % ny] += nh[j - 1]
+    w, V = np.linalg.eigh(-L)
+    wt = (V.T @ u0) ** 2
+    return min(w[i] for i in range(ny) if wt[i] > 1e-8 * wt.sum() and w[i] > 1e-12)
+
+
+def stratified_shear_case(ny, ta, tb, collision):
+    nx = 4
+    p = wl.params(nx, ny, ta, tb, collision, zero_u_feq=0)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    phi0 = -np.tanh((y - ny / 4) / np.sqrt(2)) * np.tanh((y - 3 * ny / 4) / np.sqrt(2))
+    inp = dict(solid=np.zeros((ny, nx), np.uint8), dphi=None, phi0=phi0,
+               rho0=np.ones((ny, nx)), ux0=1e-3 * np.sin(2 * np.pi * y / ny),
+               uy0=np.zeros((ny, nx)))
+    return p, inp
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("ta, tb", [(1.3, 0.7), (2.0, 0.6)])
+def test_stratified_shear_decay_through_interfaces(collision, ta, tb):
+    """tau(phi) where phi varies: a periodic stripe (two flat interfaces across y)
+    with a shear flow along them stays flat, and its velocity obeys
+    d_t u = d_y(nu(y) d_y u). The late-time decay of the kinetic energy equals
+    twice the slowest rate of that operator built from the measured phi(y) and
+    Eq. (tau), among the modes the initial sine excites (viscosity ratios 4 and
+    15; measured within 0.7%)."""
+    ny = 64
+    p, inp = stratified_shear_case(ny, ta, tb, collision)
+    o = make_oracle(p, inp)
+    ts, es = [], []
+    for k in range(60):
+        o.step(100)
+        phi, rho, ux, uy = o.fields()
+        ts.append((k + 1) * 100)
+        es.append((rho[:, 0] * ux[:, 0] ** 2).sum())
+    lam = -np.polyfit(ts[30:], np.log(es[30:]), 1)[0] / 2
+    assert np.abs(uy).max() < 1e-6                 # the interfaces stay flat
+    lam0 = _slowest_excited_rate(phi[:, 0], ta, tb, np.sin(2 * np.pi * np.arange(ny) / ny))
+    assert lam / lam0 == pytest.approx(1.0, abs=0.015)
+
+
 def test_stripe_spurious_velocity_bgk():
     """Sec. V: a stripe between neutral walls, 28 x 15, tau = 10, has a steady
     spurious flow of order 1e-3 c under BGK; with periodic y instead of walls it has
