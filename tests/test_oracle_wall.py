@@ -35,19 +35,25 @@ def _film(nx, ny, d_lo, d_hi, thickness):
                 ux0=np.zeros((ny, nx)), uy0=np.zeros((ny, nx)))
 
 
+@pytest.mark.parametrize("bounce", [0, 1], ids=["midlink", "lattice_node"])
 @pytest.mark.parametrize("th_lo,th_hi", [(60.0, 110.0), (135.0, 45.0), (90.0, 90.0)])
-def test_wall_film_reaches_the_discrete_wall_equilibrium(one_thread, th_lo, th_hi):
+def test_wall_film_reaches_the_discrete_wall_equilibrium(one_thread, th_lo, th_hi, bounce):
     """A film of phi = +1 on the bottom wall under phi = -1, between two flat
     wetting walls: the oracle's steady state is the discrete equilibrium of the
     wall problem, A phi + B phi^3 - kappa lap phi = mu0 on every fluid row with the
     ghost rows phi_0 = phi_1 - d_perp phi (Sec. II, R4), solved independently by
     Newton at the same total phi. A wrong ghost sign, a missing factor, the wall
     gradient on the wrong side of the plane or a wall-row stencil error each move
-    the profile by 1e-2 or more; nothing flows."""
+    the profile by 1e-2 or more; nothing flows.
+
+    Lattice-node bounce-back (Fig. 9b) only delays the populations that meet a
+    wall by one step, so at rest it must settle on the same equilibrium (measured
+    within 7e-11); a reflection that lost or misdirected a population would leave
+    the film off it, or flowing."""
     nx, ny = 4, 40
     d_lo, d_hi = an.theory_dphi(th_lo, KAPPA, A_L), an.theory_dphi(th_hi, KAPPA, A_L)
     p = wl.params(nx, ny, 1.0, 1.0, "bgk", Gamma=2.0)
-    o = make_oracle(p, _film(nx, ny, d_lo, d_hi, 14.0))
+    o = make_oracle(p, _film(nx, ny, d_lo, d_hi, 14.0), bounce=bounce)
     o.step(80000)
     phi, rho, ux, uy = o.fields()
     prof, mu0 = an.wall_film_profile(phi[1:ny - 1, 0], A, B, KAPPA, d_lo, d_hi)
