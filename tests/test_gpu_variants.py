@@ -226,3 +226,35 @@ def test_channel_mode_decay_between_walls_on_gpu(storage, collision, bounce):
     ratio = rate / ((tau - 0.5) / 3 * (np.pi / H) ** 2)
     say(f"  decay rate / (nu (pi/H)^2) = {ratio:.4f}")
     assert ratio == pytest.approx(1.0, abs=0.01)
+
+
+@pytest.mark.parametrize("bounce", [lbm.MIDLINK, LN])
+def test_wall_film_reaches_the_discrete_wall_equilibrium_on_gpu(bounce):
+    """On the GPU alone (FP64): a film of phi = +1 under phi = -1 between a
+    60-degree and a 110-degree wall, at rest, settles on the discrete wall
+    equilibrium (A phi + B phi^3 - kappa lap phi = mu0 on every fluid row, ghost
+    rows phi_1 - d_perp phi; Sec. II), solved by Newton at the same total phi,
+    with either bounce-back kind: lattice-node bounce-back only delays what
+    meets a wall, so its rest state is mid-link's."""
+    nx, ny = 4, 40
+    d_lo = analysis.theory_dphi(60.0, 0.04, 0.04)
+    d_hi = analysis.theory_dphi(110.0, 0.04, 0.04)
+    p = wl.params(nx, ny, 1.0, 1.0, "bgk", Gamma=2.0, bounce=bounce)
+    solid = wl.walls_mask(nx, ny)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    dphi = np.zeros((ny, nx))
+    dphi[0], dphi[ny - 1] = d_lo, d_hi
+    inp = {"solid": solid, "dphi": dphi,
+           "phi0": np.where(solid == 0, np.tanh((14.0 - y) / np.sqrt(2.0)), 0.0),
+           "rho0": np.where(solid == 0, 1.0, 0.0), "ux0": np.zeros((ny, nx)),
+           "uy0": np.zeros((ny, nx))}
+    say(f"case wall film at rest, bounce={bounce}, 80000 steps")
+    lat = gpu_lattice(p, inp)
+    lbm.lb_step(lat, 80000)
+    phi, rho, ux, uy = lbm.lb_read_fields(lat)
+    lat.close()
+    prof, _ = analysis.wall_film_profile(phi[1:ny - 1, 0], -0.04, 0.04, 0.04, d_lo, d_hi)
+    err = np.abs(phi[1:ny - 1] - prof[:, None]).max()
+    say(f"  max|phi - Newton| {err:.2e}")
+    assert err < 1e-8
+    assert np.hypot(ux, uy)[1:ny - 1].max() < 1e-10
