@@ -72,10 +72,12 @@ def test_c3_filling_record_follows_the_oracle(ratio):
 
 
 def test_c5_members_of_every_size_follow_the_oracle():
-    """The first member of each size of the 256-member ensemble (64 x 32 ..
-    512 x 256, MRT, tau_beta = 0.5 + 0.5 / ratio, tau clamp), FP32 storage in
-    one batch, against the FP64 oracle after 10^4 steps: contact angle within
-    0.5 degrees and max |d phi| <= 1e-3 (on every second row and column)."""
+    """Eight members of the 256-member ensemble (MRT, tau_beta = 0.5 + 0.5 /
+    ratio, tau clamp): the first of each size (64 x 32 .. 512 x 256) and each
+    size's member with the target angle farthest from 90 degrees (30 to 150
+    degrees, one at viscosity ratio 81), FP32 storage in one batch, against the
+    FP64 oracle after 10^4 steps: contact angle within 0.5 degrees and max
+    |d phi| <= 1e-3 (on every second row and column)."""
     z = np.load(os.path.join(GOLDEN, "c5_oracle_sample.npz"))
     n = len([k for k in z.files if k.startswith("phi")])
     descs = []
@@ -83,7 +85,8 @@ def test_c5_members_of_every_size_follow_the_oracle():
         nx, ny, seed, theta, tb = z[f"desc{k}"]
         descs.append(dict(nx=int(nx), ny=int(ny), seed=int(seed), theta=float(theta),
                           tau_beta=float(tb)))
-    assert sorted(d["nx"] for d in descs) == [64, 128, 256, 512]
+    assert n == 8 and sorted(set(d["nx"] for d in descs)) == [64, 128, 256, 512]
+    assert min(d["theta"] for d in descs) < 35.0 and max(d["theta"] for d in descs) > 145.0
     say(f"case C5 sample of {n} members, f32 batched, 10^4 steps")
     members, params = [], []
     for d in descs:
