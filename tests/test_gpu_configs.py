@@ -14,6 +14,7 @@ import pytest
 
 from oracle import analysis
 from paper_0812_1282_amd import lbm, workloads as wl
+from tests.helpers import max_u_near_contact
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -107,6 +108,42 @@ def test_c5_members_of_every_size_follow_the_oracle():
         assert abs(th - oth) <= 0.5
         assert dphi <= 1e-3
     b.close()
+
+
+def test_c2_mrt_full_length_follows_the_oracle():
+    """C2 at its stated length (256 x 128, R = 60, viscosity ratio 10, MRT with
+    Step 2, FP64) on the 30- and 150-degree walls, against the stored FP64 oracle
+    record after 20,000 steps: phi and u on every second node within 1e-9, the
+    contact angle within 1e-6 degree, the peak spurious |u| at the contact points
+    (Sec. V) within 1e-6 of its value, and sum rho, sum phi within 1e-10
+    relative. Both sides are FP64 with different summation orders; the drop is
+    close to rest, so their difference stays near rounding."""
+    z = np.load(os.path.join(GOLDEN, "c2_oracle_256x128.npz"))
+    win = tuple(float(v) for v in z["window"])
+    for k, theta in enumerate(z["thetas"]):
+        p, inp = wl.c2_drop("mrt", analysis.theory_dphi(float(theta), KAPPA, A_L), seed=201)
+        say(f"case C2 mrt {theta:.0f} degrees, {int(z['steps'])} steps, f64")
+        lat = lbm.lb_init(lbm.make_params(p, "f64"), inp["solid"], inp["phi0"],
+                          dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+        lbm.lb_step(lat, int(z["steps"]))
+        phi, rho, ux, uy = lbm.lb_read_fields(lat)
+        th = lbm.lb_contact_angle(lat, *win, 0.5, 1)["theta"]
+        lat.close()
+        fluid = inp["solid"] == 0
+        sub = fluid[::2, ::2]
+        errs = [np.abs(a[::2, ::2] - z[f"{n}{k}"])[sub].max()
+                for a, n in ((phi, "phi"), (ux, "ux"), (uy, "uy"))]
+        umax = max_u_near_contact(phi, ux, uy, inp["solid"])
+        oumax = float(z[f"umax_contact{k}"])
+        sums = np.array([rho[fluid].sum(), phi[fluid].sum()])
+        osums = z[f"sums{k}"]
+        say(f"  theta {th:.6f} (oracle {float(z[f'theta{k}']):.6f}); max|dphi|, |dux|, |duy| "
+            f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}; peak |u| at contacts {umax:.6e} "
+            f"(oracle {oumax:.6e})")
+        assert max(errs) < 1e-9
+        assert abs(th - float(z[f"theta{k}"])) < 1e-6
+        assert abs(umax - oumax) <= 1e-6 * oumax
+        assert np.all(np.abs(sums - osums) <= 1e-10 * np.abs(osums))
 
 
 def _neutral_angle(ta, tb, coll, steps):
