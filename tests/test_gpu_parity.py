@@ -81,6 +81,33 @@ def test_c1_drop_bgk_1000_steps():
     run_pair(p, inp, 1000, what="C1 100x50 BGK 60deg")
 
 
+def test_c1_configured_run_2000_steps():
+    """The 100 x 50 BGK drop on a 60-degree wall at its configured 2000 steps:
+    populations and fields within the FP64 tolerance of the oracle, the outputs
+    the run reports (contact angle, sum rho, sum phi) equal to the oracle's, and
+    sum rho, sum phi conserved from S_0 to 1e-13 relative (Sec. III)."""
+    p, inp = wl.c1_drop(seed=1, dphi_wall=D60)
+    say("case C1 100x50 BGK 60deg configured run: 2000 steps")
+    lat = gpu_lattice(p, inp)
+    orc = make_oracle(p, inp)
+    d0 = lbm.lb_diagnostics(lat)
+    lbm.lb_step(lat, 2000)
+    orc.step(2000)
+    compare(lat, orc, inp["solid"], TOL64, "C1 2000 steps")
+    win = (0.0, 100.0, 3.5, 45.5)
+    th = lbm.lb_contact_angle(lat, *win, 0.5, 1)["theta"]
+    oth = analysis.contact_angle(orc.fields()[0], inp["solid"], 0.5, 1, *win)["theta"]
+    d = lbm.lb_diagnostics(lat)
+    od = orc.diagnostics()
+    lat.close()
+    say(f"  theta {th:.9f} (oracle {oth:.9f}); sum rho {d['sum_rho']:.15e} "
+        f"(oracle {od['sum_rho']:.15e}); sum phi {d['sum_phi']:.12e} (oracle {od['sum_phi']:.12e})")
+    assert abs(th - oth) < 1e-8
+    for key in ("sum_rho", "sum_phi"):
+        assert abs(d[key] - od[key]) <= 1e-12 * abs(od[key])
+        assert abs(d[key] - d0[key]) <= 1e-13 * abs(d0[key])
+
+
 @pytest.mark.parametrize("collision,zf,zg", [("bgk", 0, 0), ("bgk", 1, 0), ("mrt", 1, 0),
                                              ("mrt", 0, 0), ("mrt", 1, 1)])
 def test_every_term_random_fields(collision, zf, zg):
