@@ -146,6 +146,30 @@ def test_c2_mrt_full_length_follows_the_oracle():
         assert np.all(np.abs(sums - osums) <= 1e-10 * np.abs(osums))
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_c2_reduced_precision_at_the_angle_extremes(storage):
+    """The precision gate away from the neutral wall: the C2 drop on the 30- and
+    150-degree walls with FP32 or FP16 shifted storage (FP32 arithmetic), after
+    20,000 steps against the stored FP64 oracle record: max |d phi| <= 1e-3 on
+    every second node and the contact angle within 0.5 degree."""
+    z = np.load(os.path.join(GOLDEN, "c2_oracle_256x128.npz"))
+    win = tuple(float(v) for v in z["window"])
+    for k, theta in enumerate(z["thetas"]):
+        p, inp = wl.c2_drop("mrt", analysis.theory_dphi(float(theta), KAPPA, A_L), seed=201)
+        say(f"case C2 mrt {theta:.0f} degrees, {int(z['steps'])} steps, {storage}")
+        lat = lbm.lb_init(lbm.make_params(p, storage), inp["solid"], inp["phi0"],
+                          dphi=inp["dphi"], rho0=inp["rho0"], ux0=inp["ux0"], uy0=inp["uy0"])
+        lbm.lb_step(lat, int(z["steps"]))
+        phi = lbm.lb_read_fields(lat)[0]
+        th = lbm.lb_contact_angle(lat, *win, 0.5, 1)["theta"]
+        lat.close()
+        sub = (inp["solid"] == 0)[::2, ::2]
+        dphi = np.abs(phi[::2, ::2] - z[f"phi{k}"])[sub].max()
+        dth = abs(th - float(z[f"theta{k}"]))
+        say(f"  max|dphi| {dphi:.2e}  dtheta {dth:.2e} degrees")
+        assert dphi <= 1e-3 and dth <= 0.5
+
+
 def _neutral_angle(ta, tb, coll, steps):
     p, inp = wl.fig2_drop(ta, tb, coll)
     lat = lbm.lb_init(lbm.make_params(p, "f64"), inp["solid"], inp["phi0"], dphi=inp["dphi"],
